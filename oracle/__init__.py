@@ -1,0 +1,226 @@
+"""FP64 CPU oracle of the coupled lattice-Boltzmann ice-growth step (Tan et al., arXiv:2101.07163).
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain, slow reference the GPU library is checked
+against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import it; the GPU library never does, and this package imports nothing from the GPU library.
+
+The forward step lives in ``snow_oracle.c`` (plain C, FP64, OpenMP over rows); this module is the
+ctypes marshalling around it plus the oracle's own parameter struct.  Population arrays use the
+canonical layout ``[q, y, x]``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libsnow_oracle.so")
+_SOURCES = ["snow_oracle.c", "snow_oracle_adj.c"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle shared library with gcc (FP64, no FMA contraction, OpenMP)."""
+    if not force and os.path.exists(_SO):
+        return _SO
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c11", "-O3", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-Wno-unused-function", "-o", tmp] + srcs + ["-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+class OrcParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("flow", ctypes.c_int32),
+        ("inout", ctypes.c_int32), ("n_fold", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+        ("lam", ctypes.c_double), ("L_sat", ctypes.c_double), ("tau_vap", ctypes.c_double),
+        ("tau_f", ctypes.c_double), ("h_drag", ctypes.c_double), ("kappa_N", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("u_in", ctypes.c_double), ("U_in", ctypes.c_double),
+        ("grad_eps2", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER
+        d = ctypes.c_double
+        dp = P(d)
+        L.orc_create.restype = ctypes.c_void_p
+        L.orc_create.argtypes = [P(OrcParams)]
+        L.orc_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_init_seed.argtypes = [ctypes.c_void_p, d, d, d, d, d, ctypes.c_void_p]
+        L.orc_set_state.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+        L.orc_get_state.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+        L.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.orc_step_count.restype = ctypes.c_int64
+        L.orc_step_count.argtypes = [ctypes.c_void_p]
+        L.orc_fields.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
+        L.orc_diag.argtypes = [ctypes.c_void_p, dp]
+        L.orc_feq.argtypes = [d, d, d, dp]
+        L.orc_geq.argtypes = [d, d, d, dp]
+        L.orc_guo.argtypes = [P(OrcParams), d, d, d, d, dp]
+        L.orc_aniso.argtypes = [P(OrcParams), d, d, dp, dp, dp]
+        L.orc_grad.argtypes = [P(OrcParams), dp, dp, dp]
+        L.orc_threads.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Params:
+    """Oracle parameter set (lattice units).  Field names follow the paper's symbols."""
+    nx: int = 128
+    ny: int = 128
+    flow: int = 0
+    inout: int = 0
+    n_fold: int = 6
+    eps: float = 0.05
+    W0: float = 1.0
+    tau0: float = 10.0
+    lam: float = 3.0
+    L_sat: float = 1.6
+    tau_vap: float = 0.8
+    tau_f: float = 0.6
+    h_drag: float = 2.757
+    kappa_N: float = 1.0
+    rho0: float = 1.0
+    u_in: float = 0.0
+    U_in: float = 0.0
+    grad_eps2: float = 1e-10
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "Params":
+        names = {f.name for f in fields(cls)}
+        return cls(**{k: v for k, v in d.items() if k in names})
+
+    def c_struct(self) -> OrcParams:
+        s = OrcParams()
+        for f in fields(self):
+            setattr(s, f.name, getattr(self, f.name))
+        return s
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Oracle:
+    """One FP64 lattice.  ``Oracle(params).init_seed(...).step(n)`` then ``fields()``."""
+
+    def __init__(self, params: Params):
+        self.p = params
+        self._cp = params.c_struct()
+        self._h = lib().orc_create(ctypes.byref(self._cp))
+        if not self._h:
+            raise ValueError("oracle: invalid parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    @property
+    def shape(self):
+        return (self.p.ny, self.p.nx)
+
+    def init_seed(self, xs, ys, R, w_init=1.0, U0=0.5, U_init: np.ndarray | None = None):
+        Ui = None if U_init is None else np.ascontiguousarray(U_init, dtype=np.float64)
+        if Ui is not None:
+            assert Ui.shape == self.shape
+        lib().orc_init_seed(self._h, float(xs), float(ys), float(R), float(w_init), float(U0),
+                            _ptr(Ui))
+        return self
+
+    def set_state(self, f=None, g=None, h=None, phip=None):
+        conv = lambda a, q: None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(
+            (q,) + self.shape if q else self.shape)
+        f, g, h, phip = conv(f, 9), conv(g, 5), conv(h, 9), conv(phip, 0)
+        lib().orc_set_state(self._h, _ptr(f), _ptr(g), _ptr(h), _ptr(phip))
+        return self
+
+    def get_state(self):
+        ny, nx = self.shape
+        f = np.empty((9, ny, nx)); g = np.empty((5, ny, nx)); h = np.empty((9, ny, nx))
+        phip = np.empty((ny, nx))
+        lib().orc_get_state(self._h, _ptr(f), _ptr(g), _ptr(h), _ptr(phip))
+        return {"f": f, "g": g, "h": h, "phip": phip}
+
+    def step(self, n: int = 1):
+        lib().orc_step(self._h, int(n))
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return int(lib().orc_step_count(self._h))
+
+    def fields(self) -> dict:
+        ny, nx = self.shape
+        out = {k: np.empty((ny, nx)) for k in ("phi", "U", "rho", "ux", "uy")}
+        lib().orc_fields(self._h, *(_ptr(out[k]) for k in ("phi", "U", "rho", "ux", "uy")))
+        return out
+
+    def diag(self) -> dict:
+        a = np.zeros(8)
+        lib().orc_diag(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        keys = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite")
+        d = dict(zip(keys, a.tolist()))
+        d["species"] = d["U"] + 0.5 * self.p.L_sat * d["phi_prev"]
+        return d
+
+
+def threads() -> int:
+    return int(lib().orc_threads())
+
+
+def feq(rho, ux, uy):
+    out = np.zeros(9)
+    lib().orc_feq(rho, ux, uy, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def geq(U, ux, uy):
+    out = np.zeros(5)
+    lib().orc_geq(U, ux, uy, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def guo(params: Params, ux, uy, Fx, Fy):
+    out = np.zeros(9)
+    cp = params.c_struct()
+    lib().orc_guo(ctypes.byref(cp), ux, uy, Fx, Fy, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def aniso(params: Params, gx, gy):
+    a, nx_, ny_ = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    cp = params.c_struct()
+    lib().orc_aniso(ctypes.byref(cp), gx, gy, ctypes.byref(a), ctypes.byref(nx_), ctypes.byref(ny_))
+    return a.value, nx_.value, ny_.value
+
+
+def grad(params: Params, phi: np.ndarray):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    assert phi.shape == (params.ny, params.nx)
+    gx = np.empty_like(phi); gy = np.empty_like(phi)
+    cp = params.c_struct()
+    P = ctypes.POINTER(ctypes.c_double)
+    lib().orc_grad(ctypes.byref(cp), phi.ctypes.data_as(P), gx.ctypes.data_as(P), gy.ctypes.data_as(P))
+    return gx, gy
