@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused coupled lattice-Boltzmann ice-growth step on one MI355X.
+
+Headline: coupled MLUPS (cells x steps / s / 1e6) of the ventilated 2048 x 2048 workload (D2Q9 flow
+with the crystal as a solid, D2Q5 vapour, phase field with 6-fold anisotropy; inlet u = 0.01, seed
+R = 8 at (300, 1024)) in FP32 storage, with all state resident in HBM.  One timed "step" is one
+coupled time step (the fused kernel, replayed from a captured HIP graph); the timed region ends with
+the FP64 conservation diagnostics.  Also reported: the HBM roofline of the step kernel (algorithmic
+bytes per launch over its measured average duration), the practical copy-kernel ceiling, 16-bit
+storage variants, and the FP64 CPU oracle timed on the host cores on a bounded sample.
+
+Prints exactly one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E published peak
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bytes_per_update(flow: bool, storage: str) -> int:
+    """Algorithmic HBM bytes per cell update: every population read once and written once, plus
+    phi_prev (FP32) read and written."""
+    npop = 23 if flow else 14
+    e = 4 if storage == "fp32" else 2
+    return npop * e * 2 + 4 * 2
+
+
+def kernel_source_sha() -> str:
+    p = os.path.join(ROOT, "paper_2101_07163_amd", "csrc", "snowlb_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def load_traffic(workload: str, storage: str):
+    """Measured HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
+    on the current kernel source; None otherwise."""
+    p = os.path.join(ROOT, "profiles", "k_step_%s_%s_traffic.txt" % (workload, storage))
+    if not os.path.exists(p):
+        return None
+    kv = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(S, torch, cfg, storage, steps, warmup, tile):
+    sim = S.Sim(cfg, storage=storage, tile=tile)
+    sim.init()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()  # the kernels are launched on this stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    diag = sim.diag()  # FP64 conservation sums; synchronises the stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = e0.elapsed_time(e1) / steps
+    return sim, wall, kernel_ms, diag
+
+
+def bw_probe(S, torch, nbytes=2 << 30, reps=10):
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    S.snowlb_bw_probe(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.snowlb_bw_probe(dst.data_ptr(), src.data_ptr(), nbytes, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(cfg, seconds):
+    import oracle
+    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
+    o.step(1)  # first-touch of the buffers outside the timed sample
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(1)
+        n += 1
+    dt = time.perf_counter() - t0
+    cells = cfg["nx"] * cfg["ny"]
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "%s, FP64 oracle, %d steps of the full %dx%d lattice from the seeded initial "
+                      "state (%.1f s)" % (cfg["name"], n, cfg["nx"], cfg["ny"], dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--tile", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the lattice would "
+              "shard by spatial domain decomposition; see the design notes). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2101_07163_amd import snowlb as S
+    from paper_2101_07163_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = {"c1": W.C1, "c2": W.C2, "c3": W.C3}[args.workload]
+    cells = cfg["nx"] * cfg["ny"]
+    flow = bool(cfg["flow"])
+
+    log("workload %s %dx%d storage %s: warmup %d, timed %d steps" % (
+        cfg["name"], cfg["nx"], cfg["ny"], args.storage, args.warmup, args.steps))
+    sim, wall, kernel_ms, diag = time_steps(S, torch, cfg, args.storage, args.steps, args.warmup, args.tile)
+    mlups = cells * args.steps / wall / 1e6
+    bpu = bytes_per_update(flow, args.storage)
+    achieved = cells * bpu / (kernel_ms * 1e-3) / 1e9
+    log("MLUPS %.1f, step kernel %.4f ms, %.0f GB/s algorithmic, tile %s" % (
+        mlups, kernel_ms, achieved, S.snowlb_tile_name(sim.tile)))
+    if diag["status"] != S.OK:
+        raise SystemExit("non-finite state after the timed steps")
+
+    traffic = load_traffic(cfg["name"], args.storage)
+    out = {
+        "metric": "coupled MLUPS and % HBM roofline at 2048^2",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "fp32" else "f32 (%s storage)" % args.storage,
+        "data": "synthetic: circular ice seed in uniform supersaturation with uniform inflow",
+        "config": {"workload": cfg["name"], "nx": cfg["nx"], "ny": cfg["ny"], "storage": args.storage,
+                   "flow": "D2Q9 inlet/outlet" if cfg.get("inout") else ("D2Q9 periodic" if flow else "off"),
+                   "u_in": cfg.get("u_in"), "eps": cfg["eps"], "tile": S.snowlb_tile_name(sim.tile)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "kernel": "k_step", "bytes_per_update": bpu,
+                     "kernel_avg_ms": round(kernel_ms, 5)},
+    }
+    del sim
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        extras = {}
+        try:
+            extras["copy_ceiling_GBps"] = round(bw_probe(S, torch), 1)
+            log("copy-kernel ceiling %.0f GB/s" % extras["copy_ceiling_GBps"])
+        except Exception as e:  # pragma: no cover
+            extras["copy_ceiling_error"] = str(e)
+        for st in ("fp16", "bf16"):
+            if st == args.storage:
+                continue
+            s2, w2, k2, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
+            b2 = bytes_per_update(flow, st)
+            extras["%s_storage" % st] = {"MLUPS": round(cells * min(args.steps, 1000) / w2 / 1e6, 1),
+                                         "kernel_avg_ms": round(k2, 5),
+                                         "GBps_algorithmic": round(cells * b2 / (k2 * 1e-3) / 1e9, 1),
+                                         "bytes_per_update": b2}
+            log("%s storage: %s" % (st, extras["%s_storage" % st]))
+            del s2
+        out["extras"] = extras
+
+    if not args.no_cpu_baseline:
+        log("CPU baseline: FP64 oracle for %.0f s" % args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        log("CPU baseline %s" % out["cpu_baseline"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

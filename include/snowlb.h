@@ -1,0 +1,163 @@
+/*
+ * snowlb.h -- C ABI of the MI355X (gfx950) coupled lattice-Boltzmann ice-crystal growth step.
+ *
+ * Method: Tan, Hosseini, Seidel-Morgenstern, Thevenin, Lorenz, "Modeling ice crystal growth using the
+ * lattice Boltzmann method" (arXiv:2101.07163).  One step advances, on a 2D lattice (dx = dt = 1):
+ *   - the D2Q9 BGK flow with the crystal as a phase-dependent solid: drag force and the velocity
+ *     projection u* = (1 - phi)/2 u (Sec. 2.2.1);
+ *   - the D2Q5 advection-diffusion-reaction LB for the supersaturation U, with the depletion source
+ *     -w (L_sat/2) d(phi)/dt and diffusivity switched off in the ice (Sec. 2.2.2, Eq. b);
+ *   - the phase-field LB of Eq. (d) with the equilibrium of Eq. (e), the 6-fold anisotropy
+ *     a_s(n) = 1 + eps cos(6 theta) (Sec. 2.1) and the isotropic E4 gradient of Table 1 (Sec. 3.1.1).
+ *
+ * Conventions
+ *   - Every function returns a snowlb_status (0 = OK) or is documented otherwise; nothing aborts or
+ *     throws across this boundary.  On error, snowlb_last_error(ctx) holds a message.
+ *   - Pointers named *_dev are device pointers (e.g. a torch tensor's data_ptr()); *_host are host
+ *     pointers.  The caller owns every buffer it passes; the library owns its context's buffers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work is enqueued
+ *     asynchronously on it unless stated otherwise.
+ *   - Fields are ny x nx, row-major, x fastest.  Population sets exchanged with the caller are in the
+ *     canonical layout [q][y][x] as FP32, whatever the internal storage.
+ *   - A context is used from one host thread at a time.
+ */
+#ifndef SNOWLB_H
+#define SNOWLB_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t snowlb_status;
+#define SNOWLB_OK 0
+#define SNOWLB_EINVAL (-1)       /* invalid argument or parameter set (checked before any GPU call) */
+#define SNOWLB_ENOMEM (-2)       /* device or host allocation failed                                */
+#define SNOWLB_EDEVICE (-3)      /* a HIP call failed; snowlb_last_error has the HIP message        */
+#define SNOWLB_EUNSUPPORTED (-4) /* valid request this build does not support                       */
+#define SNOWLB_ENONFINITE (-5)   /* a diagnostic found non-finite populations                       */
+#define SNOWLB_ESTATE (-6)       /* call out of order (e.g. step before init)                       */
+
+/* internal storage of the populations (the collision arithmetic is FP32 in all cases) */
+#define SNOWLB_STORE_FP32 0
+#define SNOWLB_STORE_FP16 1 /* FP16 deviations d = p/w - m, round-to-nearest-even: m = rho0 for
+                               f, phi(t-1) of the holding cell for h, U(t-1) of the source cell
+                               for g (kept in extra FP32 planes)                                 */
+#define SNOWLB_STORE_BF16 2 /* BF16 deviations, same encoding                                   */
+
+/* closure in x (y is always periodic) */
+#define SNOWLB_BC_PERIODIC 0
+#define SNOWLB_BC_INOUT 1 /* fixed-velocity inlet at x = 0, zero-gradient outlet at x = nx-1 (Sec. 3.1.3) */
+
+/* macroscopic fields for snowlb_read */
+#define SNOWLB_FIELD_PHI 0 /* phase field phi = sum h                                          */
+#define SNOWLB_FIELD_U 1   /* supersaturation U = sum g                                        */
+#define SNOWLB_FIELD_RHO 2 /* density sum f (0 without flow)                                  */
+#define SNOWLB_FIELD_UX 3  /* x-velocity used by the collisions (after drag and projection)    */
+#define SNOWLB_FIELD_UY 4
+
+/* population sets for snowlb_read_populations / snowlb_write_populations */
+#define SNOWLB_POP_F 0    /* 9 planes (flow; only when params.flow = 1) */
+#define SNOWLB_POP_G 1    /* 5 planes (vapour)                          */
+#define SNOWLB_POP_H 2    /* 9 planes (phase field)                     */
+#define SNOWLB_POP_PHIP 3 /* 1 plane: phi at the previous step          */
+
+typedef struct {
+    int32_t nx, ny;     /* lattice size, >= 2 each                                             */
+    int32_t flow;       /* 1: D2Q9 flow solver on; 0: u = 0 (no f populations stored)           */
+    int32_t bc_x;       /* SNOWLB_BC_PERIODIC or SNOWLB_BC_INOUT (needs flow = 1)               */
+    int32_t storage;    /* SNOWLB_STORE_*                                                       */
+    int32_t n_fold;     /* 6 (hexagonal ice, Sec. 2.1) or 4 (Sec. 3.1.2)                        */
+    double eps;         /* anisotropy strength, 0 <= eps < 0.5 (a_s = 1 + eps cos stays positive)  */
+    double W0, tau0;    /* interface width and time, > 0                                         */
+    double lambda;      /* coupling constant                                                      */
+    double L_sat;       /* depletion rate                                                         */
+    double tau_vap;     /* vapour relaxation time in the fluid, > 1/2: D = (tau_vap - 1/2)/3       */
+    double tau_f;       /* flow relaxation time, > 1/2: nu = (tau_f - 1/2)/3                       */
+    double h_drag;      /* drag constant h of the solid force (2.757)                            */
+    double kappa_N;     /* 1: flux |grad phi|^2 a da/d(grad phi); 2: |grad phi|^2 d(a^2)/d(grad phi) */
+    double rho0;        /* reference / inlet density                                              */
+    double u_in;        /* inlet x-velocity, |u_in| < 0.1                                         */
+    double U_in;        /* inlet supersaturation                                                  */
+    double grad_eps2;   /* |grad phi|^2 at or below which a = 1 and the flux N = 0 (1e-10)        */
+    double U0;          /* initial supersaturation (when no U_init field is given)                */
+    double seed_x, seed_y, seed_r; /* circular seed: centre and radius (cells)                   */
+    double init_width;  /* width of the tanh seed profile (cells)                                 */
+    int32_t diag_every; /* >0: snowlb_step checks for non-finite values every this many steps     */
+    int32_t tile;       /* step-kernel tile configuration; -1 = autotune, 0 = default            */
+} snowlb_params;
+
+typedef struct snowlb_ctx snowlb_ctx;
+
+/* Defaults: the 128^2 periodic, flow-off workload (eps 0.05, W0 1, tau0 10, lambda 3, L_sat 1.6,
+ * tau_vap 0.8, tau_f 0.6, h 2.757, kappa_N 1, seed R 5 at the centre, U0 0.5). Never fails. */
+void snowlb_params_default(snowlb_params* p);
+
+/* Validate a parameter set without touching the GPU.  EINVAL with a message in *msg_out (static
+ * storage, may be NULL) when a value is out of range. */
+snowlb_status snowlb_validate(const snowlb_params* p, const char** msg_out);
+
+/* Human-readable name of a status code (static storage). */
+const char* snowlb_status_str(snowlb_status s);
+/* Last error message of a context (valid until the next call on it); "" if none; ctx may be NULL,
+ * then the message of the last failed context-free call (snowlb_create, snowlb_bw_probe) on this
+ * thread is returned. */
+const char* snowlb_last_error(const snowlb_ctx* ctx);
+
+/* Create a context on the current HIP device: validates (EINVAL before any GPU call), then
+ * allocates two copies of the populations and phi_prev.  *out is NULL on failure. */
+snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out);
+/* Release a context (NULL-safe).  Synchronises the device first. */
+void snowlb_destroy(snowlb_ctx* ctx);
+
+/* Initial state: a circular tanh seed (phi0 = tanh((R - r)/(sqrt 2 width))), phi_prev = phi0,
+ * equilibrium populations at U_init (ny x nx device field) or at params.U0 when U_init_dev is NULL,
+ * velocity (1 - phi0)/2 (u_in, 0) for a ventilated domain and 0 otherwise.  Resets the step count. */
+snowlb_status snowlb_init(snowlb_ctx* ctx, const float* U_init_dev, void* stream);
+
+/* Advance n >= 0 steps (asynchronous).  With diag_every > 0 the host synchronises every diag_every
+ * steps and returns ENONFINITE as soon as a non-finite population is found.  ESTATE before init. */
+snowlb_status snowlb_step(snowlb_ctx* ctx, int32_t n, void* stream);
+int64_t snowlb_step_count(const snowlb_ctx* ctx);
+
+/* Write one macroscopic field (SNOWLB_FIELD_*) of the current state into dst_dev (float,
+ * dst_elems >= nx*ny, caller-owned). */
+snowlb_status snowlb_read(snowlb_ctx* ctx, int32_t field, float* dst_dev, int64_t dst_elems,
+                          void* stream);
+
+/* Copy a population set (SNOWLB_POP_*) of the current state to / from caller memory in the canonical
+ * FP32 layout [q][y][x] (elems >= Q*nx*ny).  Writing encodes into the context's storage format. */
+snowlb_status snowlb_read_populations(snowlb_ctx* ctx, int32_t set, float* dst_dev, int64_t elems,
+                                      void* stream);
+snowlb_status snowlb_write_populations(snowlb_ctx* ctx, int32_t set, const float* src_dev,
+                                       int64_t elems, void* stream);
+
+/* FP64 diagnostics of the current state, synchronous (waits for `stream`):
+ * out[0..7] = sum rho, sum jx, sum jy, sum U, sum phi, sum phi_prev, #(phi > 0), #non-finite cells.
+ * Sums are reduced in a fixed order (deterministic).  Returns ENONFINITE if out[7] > 0. */
+snowlb_status snowlb_diag(snowlb_ctx* ctx, double* out_host, void* stream);
+
+/* Checkpoint / resume: the whole state (populations, phi_prev) and the step count, as an opaque
+ * device buffer of snowlb_state_bytes() bytes.  load_state requires a buffer saved from a context
+ * with identical sizes and storage. */
+int64_t snowlb_state_bytes(const snowlb_ctx* ctx);
+snowlb_status snowlb_save_state(snowlb_ctx* ctx, void* buf_dev, int64_t bytes, void* stream);
+snowlb_status snowlb_load_state(snowlb_ctx* ctx, const void* buf_dev, int64_t bytes, void* stream);
+
+/* Step-kernel tile configurations.  snowlb_tile_count() configurations exist; snowlb_tile_name(i)
+ * describes one ("64x4" = 64 cells in x by 4 in y per workgroup).  snowlb_set_tile selects one for
+ * a context; results are bitwise identical for every configuration. */
+int32_t snowlb_tile_count(void);
+const char* snowlb_tile_name(int32_t i);
+snowlb_status snowlb_set_tile(snowlb_ctx* ctx, int32_t tile);
+int32_t snowlb_get_tile(const snowlb_ctx* ctx);
+
+/* Practical HBM ceiling probe: copy `bytes` (a multiple of 16) from src_dev to dst_dev with a plain
+ * coalesced 16-byte-per-lane grid-stride kernel on `stream`.  Used to report measured bandwidth next
+ * to the published peak, and to calibrate byte counters.  Buffers must not overlap. */
+snowlb_status snowlb_bw_probe(void* dst_dev, const void* src_dev, int64_t bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,72 @@
+// snowlb_internal.h -- descriptors shared by the HIP kernels and the host runtime of libsnowlb.
+//
+// Device layout (per domain): structure-of-arrays population planes, each ny rows of `pitch`
+// elements (x fastest, pitch a multiple of 64 elements so every row starts 256-byte aligned),
+// consecutive planes `plane` elements apart (padded and staggered so that the 23 streams of one
+// tile do not start on the same HBM channel).  Plane order: f_0..f_8 (flow only), g_0..g_4,
+// h_0..h_8.  Two copies (pop[0], pop[1]) ping-pong between steps, and so do the FP32 planes
+// phi_prev and (16-bit storage only) U_prev, which neighbours read as encoding references.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snowlb {
+
+struct DomDesc {
+    int32_t nx, ny, pitch, npop;  // npop: planes per copy (23 with flow, 14 without)
+    int64_t plane;                // elements between consecutive planes
+    void* pop[2];                 // the two population copies
+    float* phip[2];               // phi(t-1), FP32, pitched
+    float* uprev[2];              // U(t-1), FP32, pitched (16-bit storage only, else null)
+    double grad_eps2;             // |grad phi|^2 (FP64) at or below which a = 1 and N = 0
+    int32_t off_g, off_h;         // plane index of g_0 and h_0
+    int32_t n_fold, storage;
+    int32_t inout, pad0;          // x closure: 1 = inlet/outlet
+    // physics in FP32 (lattice units)
+    float eps;          // anisotropy strength
+    float Dphi;         // W0^2 / tau0
+    float aniso_coef;   // kappa_N * Dphi * n_fold * eps  (flux N = coef * a * S_n * (gy, -gx))
+    float inv_tau0;
+    float lam;
+    float half_Lsat;    // L_sat / 2
+    float tauv_m_half;  // tau_vap - 1/2
+    float omega_f;      // 1 / tau_f
+    float guo;          // 1 - 1/(2 tau_f)
+    float kdrag;        // h nu / (4 W0^2), nu = (tau_f - 1/2)/3
+    float ref_f;        // 16-bit storage reference of f (rho0)
+    float U_in;         // inlet supersaturation (also the reference of g streamed from the inlet)
+    float f_in[9];      // inlet ghost populations f_eq(rho0, (u_in, 0))
+    float g_in[5];      // inlet ghost populations g_eq(U_in, (u_in, 0))
+    float pad_[3];
+};
+
+struct TileDesc {
+    int32_t dom, x0, y0, pad;
+};
+
+// Launchers (defined in snowlb_kernels.hip).  All are asynchronous on `stream` and return the
+// hipError_t of the launch.
+int tile_config_count();
+const char* tile_config_name(int i);
+int tile_config_tx(int i);
+int tile_config_ty(int i);
+// One step of every tile in `tiles` (device array of ntiles entries), reading copy `par` and writing
+// copy 1 - par.  `flow`, `inout`, `storage` must be the same for every domain referenced.
+hipError_t launch_step(int tile_cfg, int storage, int flow, int inout, const DomDesc* doms_dev,
+                       const TileDesc* tiles_dev, int ntiles, int grid, int par, hipStream_t s);
+// Persistent grid size used for a launch of `ntiles` tiles with configuration `tile_cfg`.
+int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout);
+
+hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float seed_x,
+                       float seed_y, float seed_r, float width, float rho0, float u_in, hipStream_t s);
+hipError_t launch_read(const DomDesc& d, int par, int field, float* dst, hipStream_t s);
+hipError_t launch_pop_io(const DomDesc& d, int par, int set, int to_canonical, float* canon,
+                         hipStream_t s);
+// FP64 diagnostics: partials (nblk x 8 doubles) then out[8]; returns the number of blocks used via
+// diag_blocks().
+int diag_blocks(const DomDesc& d);
+hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out, hipStream_t s);
+
+hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
+
+}  // namespace snowlb

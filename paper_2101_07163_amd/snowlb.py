@@ -1,0 +1,310 @@
+"""Thin Python binding of libsnowlb (include/snowlb.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of libsnowlb.  The
+functions ``snowlb_*`` below carry the names and arguments of the C ABI; ``Sim`` is a convenience
+object around one context that takes device memory and streams from PyTorch.  Importing this
+module does not touch the GPU; loading the library fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, fields
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libsnowlb.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+STORE_FP32, STORE_FP16, STORE_BF16 = 0, 1, 2
+BC_PERIODIC, BC_INOUT = 0, 1
+FIELD_PHI, FIELD_U, FIELD_RHO, FIELD_UX, FIELD_UY = 0, 1, 2, 3, 4
+POP_F, POP_G, POP_H, POP_PHIP = 0, 1, 2, 3
+FIELDS = {"phi": FIELD_PHI, "U": FIELD_U, "rho": FIELD_RHO, "ux": FIELD_UX, "uy": FIELD_UY}
+POPS = {"f": (POP_F, 9), "g": (POP_G, 5), "h": (POP_H, 9), "phip": (POP_PHIP, 1)}
+STORAGES = {"fp32": STORE_FP32, "fp16": STORE_FP16, "bf16": STORE_BF16}
+
+
+class SnowlbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+class snowlb_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("flow", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("storage", ctypes.c_int32), ("n_fold", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+        ("lam", ctypes.c_double), ("L_sat", ctypes.c_double), ("tau_vap", ctypes.c_double),
+        ("tau_f", ctypes.c_double), ("h_drag", ctypes.c_double), ("kappa_N", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("u_in", ctypes.c_double), ("U_in", ctypes.c_double),
+        ("grad_eps2", ctypes.c_double), ("U0", ctypes.c_double),
+        ("seed_x", ctypes.c_double), ("seed_y", ctypes.c_double), ("seed_r", ctypes.c_double),
+        ("init_width", ctypes.c_double), ("diag_every", ctypes.c_int32), ("tile", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+# exported symbol -> (restype, argtypes); the CPU-only ABI test checks this table against the header
+_P = ctypes.POINTER
+_v = ctypes.c_void_p
+_SIGS = {
+    "snowlb_params_default": (None, [_P(snowlb_params)]),
+    "snowlb_validate": (ctypes.c_int32, [_P(snowlb_params), _P(ctypes.c_char_p)]),
+    "snowlb_status_str": (ctypes.c_char_p, [ctypes.c_int32]),
+    "snowlb_last_error": (ctypes.c_char_p, [_v]),
+    "snowlb_create": (ctypes.c_int32, [_P(snowlb_params), _P(_v)]),
+    "snowlb_destroy": (None, [_v]),
+    "snowlb_init": (ctypes.c_int32, [_v, _v, _v]),
+    "snowlb_step": (ctypes.c_int32, [_v, ctypes.c_int32, _v]),
+    "snowlb_step_count": (ctypes.c_int64, [_v]),
+    "snowlb_read": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb_read_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb_write_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb_diag": (ctypes.c_int32, [_v, _P(ctypes.c_double), _v]),
+    "snowlb_state_bytes": (ctypes.c_int64, [_v]),
+    "snowlb_save_state": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
+    "snowlb_load_state": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
+    "snowlb_tile_count": (ctypes.c_int32, []),
+    "snowlb_tile_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "snowlb_set_tile": (ctypes.c_int32, [_v, ctypes.c_int32]),
+    "snowlb_get_tile": (ctypes.c_int32, [_v]),
+    "snowlb_bw_probe": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
+}
+
+
+def lib():
+    """Load libsnowlb.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsnowlb.so is not built (%s); run __graft_entry__.build() or "
+                               "python -m paper_2101_07163_amd.build" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().snowlb_status_str(s).decode()
+    except Exception:  # pragma: no cover
+        return "status %d" % s
+
+
+def _check(status: int, ctx=None):
+    if status != OK:
+        msg = lib().snowlb_last_error(ctx).decode()
+        raise SnowlbError(status, msg)
+
+
+# ----------------------------------------------------------------------------- C-ABI, same names
+
+def snowlb_params_default() -> snowlb_params:
+    p = snowlb_params()
+    lib().snowlb_params_default(ctypes.byref(p))
+    return p
+
+
+def snowlb_validate(p: snowlb_params) -> tuple[int, str]:
+    msg = ctypes.c_char_p()
+    s = lib().snowlb_validate(ctypes.byref(p), ctypes.byref(msg))
+    return s, (msg.value or b"").decode()
+
+
+def snowlb_create(p: snowlb_params) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().snowlb_create(ctypes.byref(p), ctypes.byref(ctx)), None)
+    return ctx
+
+
+def snowlb_destroy(ctx) -> None:
+    lib().snowlb_destroy(ctx)
+
+
+def snowlb_init(ctx, U_init_dev: int | None, stream: int) -> None:
+    _check(lib().snowlb_init(ctx, U_init_dev, stream), ctx)
+
+
+def snowlb_step(ctx, n: int, stream: int) -> None:
+    _check(lib().snowlb_step(ctx, int(n), stream), ctx)
+
+
+def snowlb_step_count(ctx) -> int:
+    return int(lib().snowlb_step_count(ctx))
+
+
+def snowlb_read(ctx, field: int, dst_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb_read(ctx, field, dst_dev, elems, stream), ctx)
+
+
+def snowlb_read_populations(ctx, pset: int, dst_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb_read_populations(ctx, pset, dst_dev, elems, stream), ctx)
+
+
+def snowlb_write_populations(ctx, pset: int, src_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb_write_populations(ctx, pset, src_dev, elems, stream), ctx)
+
+
+def snowlb_diag(ctx, stream: int) -> tuple[int, list]:
+    out = (ctypes.c_double * 8)()
+    s = lib().snowlb_diag(ctx, out, stream)
+    if s not in (OK, ENONFINITE):
+        _check(s, ctx)
+    return s, list(out)
+
+
+def snowlb_state_bytes(ctx) -> int:
+    return int(lib().snowlb_state_bytes(ctx))
+
+
+def snowlb_save_state(ctx, buf_dev: int, nbytes: int, stream: int) -> None:
+    _check(lib().snowlb_save_state(ctx, buf_dev, nbytes, stream), ctx)
+
+
+def snowlb_load_state(ctx, buf_dev: int, nbytes: int, stream: int) -> None:
+    _check(lib().snowlb_load_state(ctx, buf_dev, nbytes, stream), ctx)
+
+
+def snowlb_tile_count() -> int:
+    return int(lib().snowlb_tile_count())
+
+
+def snowlb_tile_name(i: int) -> str:
+    return lib().snowlb_tile_name(i).decode()
+
+
+def snowlb_set_tile(ctx, tile: int) -> None:
+    _check(lib().snowlb_set_tile(ctx, tile), ctx)
+
+
+def snowlb_get_tile(ctx) -> int:
+    return int(lib().snowlb_get_tile(ctx))
+
+
+def snowlb_bw_probe(dst_dev: int, src_dev: int, nbytes: int, stream: int) -> None:
+    _check(lib().snowlb_bw_probe(dst_dev, src_dev, nbytes, stream), None)
+
+
+# ----------------------------------------------------------------------------- convenience object
+
+def make_params(cfg: dict, storage: str | int = "fp32", tile: int = 0, diag_every: int = 0) -> snowlb_params:
+    """snowlb_params from a workload dict (keys as in workloads.py)."""
+    p = snowlb_params_default()
+    p.nx, p.ny = int(cfg["nx"]), int(cfg["ny"])
+    p.flow = int(cfg.get("flow", 0))
+    p.bc_x = int(cfg.get("inout", 0))
+    p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    p.n_fold = int(cfg.get("n_fold", 6))
+    for k in ("eps", "W0", "tau0", "lam", "L_sat", "tau_vap", "tau_f", "h_drag", "kappa_N", "rho0",
+              "u_in", "U_in", "grad_eps2", "U0"):
+        if k in cfg:
+            setattr(p, k, float(cfg[k]))
+    sx, sy, R = cfg.get("seed", (p.nx / 2, p.ny / 2, 5.0))
+    p.seed_x, p.seed_y, p.seed_r = float(sx), float(sy), float(R)
+    p.init_width = float(cfg.get("w_init", 1.0))
+    p.tile = int(tile)
+    p.diag_every = int(diag_every)
+    return p
+
+
+class Sim:
+    """One lattice on the current GPU.  Buffers passed in and out are torch CUDA tensors."""
+
+    def __init__(self, cfg: dict | snowlb_params, storage: str | int = "fp32", tile: int = 0,
+                 diag_every: int = 0):
+        import torch
+        self.torch = torch
+        self.p = cfg if isinstance(cfg, snowlb_params) else make_params(cfg, storage, tile, diag_every)
+        self.ctx = snowlb_create(self.p)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                snowlb_destroy(ctx)
+            except Exception:  # interpreter shutdown: module globals may already be gone
+                pass
+            self.ctx = None
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    @property
+    def shape(self):
+        return (self.p.ny, self.p.nx)
+
+    def init(self, U_init=None):
+        ptr = None
+        if U_init is not None:
+            U_init = self.torch.as_tensor(U_init, dtype=self.torch.float32, device="cuda").contiguous()
+            assert tuple(U_init.shape) == self.shape
+            self._U_init = U_init  # keep alive until the kernel ran
+            ptr = U_init.data_ptr()
+        snowlb_init(self.ctx, ptr, self.stream)
+        return self
+
+    def step(self, n: int = 1):
+        snowlb_step(self.ctx, n, self.stream)
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return snowlb_step_count(self.ctx)
+
+    def read(self, field: str):
+        out = self.torch.empty(self.shape, dtype=self.torch.float32, device="cuda")
+        snowlb_read(self.ctx, FIELDS[field], out.data_ptr(), out.numel(), self.stream)
+        return out
+
+    def read_populations(self, name: str):
+        pset, q = POPS[name]
+        out = self.torch.empty((q,) + self.shape, dtype=self.torch.float32, device="cuda")
+        snowlb_read_populations(self.ctx, pset, out.data_ptr(), out.numel(), self.stream)
+        return out if q > 1 else out[0]
+
+    def write_populations(self, name: str, values):
+        pset, q = POPS[name]
+        t = self.torch.as_tensor(values, dtype=self.torch.float32, device="cuda").reshape(
+            (q,) + self.shape).contiguous()
+        snowlb_write_populations(self.ctx, pset, t.data_ptr(), t.numel(), self.stream)
+        self.torch.cuda.current_stream().synchronize()
+        return self
+
+    def set_state(self, f=None, g=None, h=None, phip=None):
+        for name, v in (("f", f), ("g", g), ("h", h), ("phip", phip)):
+            if v is not None:
+                self.write_populations(name, v)
+        return self
+
+    def diag(self) -> dict:
+        s, v = snowlb_diag(self.ctx, self.stream)
+        keys = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite")
+        d = dict(zip(keys, v))
+        d["species"] = d["U"] + 0.5 * self.p.L_sat * d["phi_prev"]
+        d["status"] = s
+        return d
+
+    def save_state(self):
+        n = snowlb_state_bytes(self.ctx)
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+        snowlb_save_state(self.ctx, buf.data_ptr(), n, self.stream)
+        return buf
+
+    def load_state(self, buf):
+        snowlb_load_state(self.ctx, buf.data_ptr(), buf.numel(), self.stream)
+        return self
+
+    def set_tile(self, tile: int):
+        snowlb_set_tile(self.ctx, tile)
+        return self
+
+    @property
+    def tile(self) -> int:
+        return snowlb_get_tile(self.ctx)

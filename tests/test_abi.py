@@ -1,0 +1,84 @@
+"""C-ABI contract of libsnowlb, CPU only: the library loads, exports every function the header
+declares, and rejects invalid parameters before any GPU call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2101_07163_amd import snowlb as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "snowlb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(snowlb_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported_and_bound():
+    L = S.lib()
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n           # exported by the shared library
+        assert n in S._SIGS, n            # bound by the Python binding with the same name
+
+
+def test_status_strings():
+    for code, name in ((0, "SNOWLB_OK"), (-1, "SNOWLB_EINVAL"), (-5, "SNOWLB_ENONFINITE"),
+                       (-6, "SNOWLB_ESTATE")):
+        assert S.lib().snowlb_status_str(code).decode() == name
+
+
+def test_defaults_are_valid():
+    p = S.snowlb_params_default()
+    assert S.snowlb_validate(p) == (0, "")
+    assert (p.nx, p.ny, p.n_fold) == (128, 128, 6)
+
+
+@pytest.mark.parametrize("field,value,frag", [
+    ("nx", 1, "nx and ny"), ("ny", 0, "nx and ny"), ("tau_vap", 0.5, "tau_vap"),
+    ("n_fold", 5, "n_fold"), ("storage", 3, "storage"), ("eps", 0.6, "eps"),
+    ("W0", 0.0, "W0"), ("tile", 99, "tile"), ("diag_every", -1, "diag_every"),
+    ("eps", float("nan"), "non-finite"), ("init_width", 0.0, "init_width"),
+])
+def test_invalid_params_rejected_before_gpu(field, value, frag):
+    p = S.snowlb_params_default()
+    setattr(p, field, value)
+    st, msg = S.snowlb_validate(p)
+    assert st == S.EINVAL and frag in msg
+    ctx = ctypes.c_void_p(123)
+    st = S.lib().snowlb_create(ctypes.byref(p), ctypes.byref(ctx))
+    assert st == S.EINVAL and not ctx.value
+    assert frag in S.lib().snowlb_last_error(None).decode()
+
+
+def test_flow_dependent_rules():
+    p = S.snowlb_params_default()
+    p.bc_x = S.BC_INOUT
+    assert S.snowlb_validate(p)[0] == S.EINVAL       # inflow/outflow needs the flow solver
+    p.flow = 1
+    assert S.snowlb_validate(p)[0] == S.OK
+    p.u_in = 0.2
+    assert S.snowlb_validate(p)[0] == S.EINVAL       # Mach limit
+    p.u_in = 0.01
+    p.tau_f = 0.5
+    assert S.snowlb_validate(p)[0] == S.EINVAL
+
+
+def test_null_arguments():
+    L = S.lib()
+    assert L.snowlb_create(None, None) == S.EINVAL
+    assert L.snowlb_step(None, 1, None) == S.EINVAL
+    assert L.snowlb_step_count(None) == -1
+    L.snowlb_destroy(None)
+
+
+def test_tile_configurations():
+    n = S.snowlb_tile_count()
+    assert n >= 4
+    names = [S.snowlb_tile_name(i) for i in range(n)]
+    assert all(re.fullmatch(r"\d+x\d+", s) for s in names)
+    assert S.lib().snowlb_tile_name(n).decode() == "?"
