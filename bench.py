@@ -32,10 +32,12 @@ def log(*a):
 
 def bytes_per_update(flow: bool, storage: str) -> int:
     """Algorithmic HBM bytes per cell update: every population read once and written once, plus
-    phi_prev (FP32) read and written."""
+    phi_prev (FP32) read and written; 16-bit storage also reads and writes the cell's 16-bit
+    reference values (U, and rho, jx, jy with flow)."""
     npop = 23 if flow else 14
     e = 4 if storage == "fp32" else 2
-    return npop * e * 2 + 4 * 2
+    refs = 0 if storage == "fp32" else (4 if flow else 1) * 2 * 2
+    return npop * e * 2 + 4 * 2 + refs
 
 
 def kernel_source_sha() -> str:
@@ -127,6 +129,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="copy,fp16,bf16",
+                    help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -186,13 +190,13 @@ def main():
 
     if not args.no_extras:
         extras = {}
-        try:
+        wanted = set(x for x in args.extras.split(",") if x)
+        if "copy" in wanted:
             extras["copy_ceiling_GBps"] = round(bw_probe(S, torch), 1)
+            extras["copy_probe_bytes"] = 2 << 30
             log("copy-kernel ceiling %.0f GB/s" % extras["copy_ceiling_GBps"])
-        except Exception as e:  # pragma: no cover
-            extras["copy_ceiling_error"] = str(e)
         for st in ("fp16", "bf16"):
-            if st == args.storage:
+            if st == args.storage or st not in wanted:
                 continue
             s2, w2, k2, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
             b2 = bytes_per_update(flow, st)

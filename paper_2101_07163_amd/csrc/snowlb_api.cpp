@@ -56,9 +56,9 @@ struct snowlb_ctx {
     int esize = 4;
     DomDesc dom{};
     DomDesc* d_dom = nullptr;
-    void* mem = nullptr;  // one allocation: pop[0], pop[1], phip[0], phip[1], uprev[0], uprev[1]
-    int64_t pop_bytes = 0, phip_bytes = 0;
-    bool local_ref = false;  // 16-bit storage: U_prev planes exist
+    void* mem = nullptr;  // one allocation: pop[0], pop[1], phip[0], phip[1], refs[0], refs[1]
+    int64_t pop_bytes = 0, phip_bytes = 0, refs_bytes = 0;
+    bool local_ref = false;  // 16-bit storage: reference planes exist
     double* d_partials = nullptr;
     double* d_out = nullptr;
     double* h_out = nullptr;      // pinned, 8 doubles
@@ -157,6 +157,7 @@ void fill_dom(snowlb_ctx* c) {
     d.grad_eps2 = p.grad_eps2;
     d.ref_f = (float)p.rho0;
     d.U_in = (float)p.U_in;
+    d.u_in = (float)p.u_in;
     const double u = p.u_in;
     for (int q = 0; q < 9; ++q) {
         const double cu = kCX[q] * u;
@@ -427,20 +428,26 @@ snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out) {
     c->pop_bytes = round_up(plane_bytes * c->dom.npop, 65536);
     c->phip_bytes = round_up(pitch * p->ny * 4, 65536) + env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
     c->local_ref = p->storage != SNOWLB_STORE_FP32;
-    const int nextra = c->local_ref ? 4 : 2;
-    e = hipMalloc(&c->mem, (size_t)(2 * c->pop_bytes + nextra * c->phip_bytes));
+    int64_t rplane_bytes = 0;
+    if (c->local_ref) {
+        rplane_bytes = round_up(pitch * p->ny * c->esize, 65536) + env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
+        c->refs_bytes = round_up(rplane_bytes * (p->flow ? 4 : 1), 65536);
+    }
+    const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
+    e = hipMalloc(&c->mem, (size_t)total);
     if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(state)"));
-    // zero everything once: the 16-bit encodings reference phi_prev / U_prev, which must be defined
-    // even before the caller writes them
-    e = hipMemset(c->mem, 0, (size_t)(2 * c->pop_bytes + nextra * c->phip_bytes));
+    // zero everything once: the 16-bit encodings reference phi_prev and the reference planes, which
+    // must be defined even before the caller writes them
+    e = hipMemset(c->mem, 0, (size_t)total);
     if (e != hipSuccess) return bail(hip_fail(c, e, "hipMemset(state)"));
     char* base = (char*)c->mem;
     c->dom.pop[0] = base;
     c->dom.pop[1] = base + c->pop_bytes;
     c->dom.phip[0] = (float*)(base + 2 * c->pop_bytes);
     c->dom.phip[1] = (float*)(base + 2 * c->pop_bytes + c->phip_bytes);
-    c->dom.uprev[0] = c->local_ref ? (float*)(base + 2 * c->pop_bytes + 2 * c->phip_bytes) : nullptr;
-    c->dom.uprev[1] = c->local_ref ? (float*)(base + 2 * c->pop_bytes + 3 * c->phip_bytes) : nullptr;
+    c->dom.refs[0] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes : nullptr;
+    c->dom.refs[1] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes + c->refs_bytes : nullptr;
+    c->dom.rplane = rplane_bytes / c->esize;
 
     e = hipMalloc(&c->d_dom, sizeof(DomDesc));
     if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(desc)"));
@@ -490,8 +497,7 @@ snowlb_status snowlb_init(snowlb_ctx* c, const float* U_init_dev, void* stream) 
     const snowlb_params& p = c->p;
     c->par = 0;
     hipError_t e = launch_init(c->dom, 0, U_init_dev, (float)p.U0, (float)p.seed_x, (float)p.seed_y,
-                               (float)p.seed_r, (float)p.init_width, (float)p.rho0, (float)p.u_in,
-                               (hipStream_t)stream);
+                               (float)p.seed_r, (float)p.init_width, (float)p.u_in, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "init kernel");
     c->step = 0;
     c->inited = true;
@@ -570,7 +576,7 @@ snowlb_status snowlb_diag(snowlb_ctx* c, double* out, void* stream) {
 }
 
 int64_t snowlb_state_bytes(const snowlb_ctx* c) {
-    return c ? kHeaderBytes + c->pop_bytes + (c->local_ref ? 2 : 1) * c->phip_bytes : -1;
+    return c ? kHeaderBytes + c->pop_bytes + c->phip_bytes + c->refs_bytes : -1;
 }
 
 snowlb_status snowlb_save_state(snowlb_ctx* c, void* buf, int64_t bytes, void* stream) {
@@ -595,8 +601,8 @@ snowlb_status snowlb_save_state(snowlb_ctx* c, void* buf, int64_t bytes, void* s
     HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes, c->dom.phip[c->par], c->phip_bytes,
                              hipMemcpyDeviceToDevice, s));
     if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->dom.uprev[c->par],
-                                 c->phip_bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->dom.refs[c->par],
+                                 c->refs_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return SNOWLB_OK;
 }
@@ -616,8 +622,8 @@ snowlb_status snowlb_load_state(snowlb_ctx* c, const void* buf, int64_t bytes, v
     HIPCHK(c, hipMemcpyAsync(c->dom.phip[0], b + kHeaderBytes + c->pop_bytes, c->phip_bytes,
                              hipMemcpyDeviceToDevice, s));
     if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(c->dom.uprev[0], b + kHeaderBytes + c->pop_bytes + c->phip_bytes,
-                                 c->phip_bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->dom.refs[0], b + kHeaderBytes + c->pop_bytes + c->phip_bytes,
+                                 c->refs_bytes, hipMemcpyDeviceToDevice, s));
     c->par = 0;
     c->step = h->step;
     c->inited = true;

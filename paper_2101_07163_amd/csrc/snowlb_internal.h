@@ -4,8 +4,9 @@
 // elements (x fastest, pitch a multiple of 64 elements so every row starts 256-byte aligned),
 // consecutive planes `plane` elements apart (padded and staggered so that the 23 streams of one
 // tile do not start on the same HBM channel).  Plane order: f_0..f_8 (flow only), g_0..g_4,
-// h_0..h_8.  Two copies (pop[0], pop[1]) ping-pong between steps, and so do the FP32 planes
-// phi_prev and (16-bit storage only) U_prev, which neighbours read as encoding references.
+// h_0..h_8.  Two copies (pop[0], pop[1]) ping-pong between steps, and so do the FP32 plane phi_prev
+// and (16-bit storage only) the 16-bit reference planes U, rho, jx, jy that neighbours read to
+// decode the populations a cell emitted.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,7 +18,8 @@ struct DomDesc {
     int64_t plane;                // elements between consecutive planes
     void* pop[2];                 // the two population copies
     float* phip[2];               // phi(t-1), FP32, pitched
-    float* uprev[2];              // U(t-1), FP32, pitched (16-bit storage only, else null)
+    void* refs[2];                // 16-bit storage only: reference planes U, rho, jx, jy (else null)
+    int64_t rplane;               // elements between consecutive reference planes
     double grad_eps2;             // |grad phi|^2 (FP64) at or below which a = 1 and N = 0
     int32_t off_g, off_h;         // plane index of g_0 and h_0
     int32_t n_fold, storage;
@@ -34,7 +36,8 @@ struct DomDesc {
     float guo;          // 1 - 1/(2 tau_f)
     float kdrag;        // h nu / (4 W0^2), nu = (tau_f - 1/2)/3
     float ref_f;        // 16-bit storage reference of f (rho0)
-    float U_in;         // inlet supersaturation (also the reference of g streamed from the inlet)
+    float U_in;         // inlet supersaturation
+    float u_in;         // inlet x-velocity
     float f_in[9];      // inlet ghost populations f_eq(rho0, (u_in, 0))
     float g_in[5];      // inlet ghost populations g_eq(U_in, (u_in, 0))
     float pad_[3];
@@ -58,7 +61,7 @@ hipError_t launch_step(int tile_cfg, int storage, int flow, int inout, const Dom
 int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout);
 
 hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float seed_x,
-                       float seed_y, float seed_r, float width, float rho0, float u_in, hipStream_t s);
+                       float seed_y, float seed_r, float width, float u_in, hipStream_t s);
 hipError_t launch_read(const DomDesc& d, int par, int field, float* dst, hipStream_t s);
 hipError_t launch_pop_io(const DomDesc& d, int par, int set, int to_canonical, float* canon,
                          hipStream_t s);

@@ -20,14 +20,16 @@
 //
 // 16-bit storage keeps each population as a deviation d = p / w - m from a local reference m
 // (collision arithmetic stays FP32):
-//   f : m = rho0;
-//   h : m = phi(t-1) of the cell that holds the population (its phi_prev; the writer knows it from
-//       the LDS phi of the destination, the reader from its phi_prev plane);
-//   g : m = U(t-1) of the cell the population streamed from (the writer uses its own U; the reader
-//       stages the U_prev plane with the halo).
-// The deviations are then small (time changes and non-equilibrium parts), so the 16-bit rounding
-// error is small in absolute terms.  phi_prev and U_prev are FP32 planes in two copies, because
-// neighbours read them.
+//   h   : m = phi(t-1) of the cell that holds the population (its phi_prev; the writer knows it from
+//         the LDS phi of the destination, the reader from its phi_prev plane);
+//   g_q : m = U of the cell the population streamed from;
+//   f_q : m = rho + 3 c_q . j of the cell the population streamed from (its first-order equilibrium,
+//         so the velocity term leaves the deviation).
+// The source cell stores its U, rho, jx, jy rounded to the 16-bit format in reference planes; writer
+// and reader use exactly those rounded values (the reader stages them with the halo), so any
+// rounding of the references cancels.  The deviations are then small (time changes and
+// non-equilibrium parts), and so is the 16-bit rounding error in absolute terms.  phi_prev and the
+// reference planes come in two copies, because neighbours read them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -53,6 +55,8 @@ struct StoreF32 {
     static constexpr bool kLocalRef = false;
     static __device__ __forceinline__ float dec(T v, float, float) { return v; }
     static __device__ __forceinline__ T enc(float p, float, float) { return p; }
+    static __device__ __forceinline__ T to_ref(float v) { return v; }
+    static __device__ __forceinline__ float from_ref(T v) { return v; }
 };
 struct StoreF16 {
     using T = _Float16;
@@ -61,6 +65,8 @@ struct StoreF16 {
     static __device__ __forceinline__ T enc(float p, float iw, float ref) {
         return (_Float16)(p * iw - ref);  // v_cvt_f16_f32: round to nearest even
     }
+    static __device__ __forceinline__ T to_ref(float v) { return (_Float16)v; }
+    static __device__ __forceinline__ float from_ref(T v) { return (float)v; }
 };
 struct StoreBF16 {
     using T = uint16_t;
@@ -68,13 +74,24 @@ struct StoreBF16 {
     static __device__ __forceinline__ float dec(T v, float w, float ref) {
         return w * (ref + __uint_as_float((uint32_t)v << 16));
     }
-    static __device__ __forceinline__ T enc(float p, float iw, float ref) {
-        uint32_t u = __float_as_uint(p * iw - ref);
+    static __device__ __forceinline__ T enc(float p, float iw, float ref) { return to_ref(p * iw - ref); }
+    static __device__ __forceinline__ T to_ref(float v) {
+        uint32_t u = __float_as_uint(v);
         if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
         u += 0x7fffu + ((u >> 16) & 1u);                                     // nearest even
         return (T)(u >> 16);
     }
+    static __device__ __forceinline__ float from_ref(T v) { return __uint_as_float((uint32_t)v << 16); }
 };
+
+// Reference of a 16-bit f_q: rho + 3 c_q . j of its source, with one explicit fused rounding so
+// that the writer and every reader produce the same bits.
+__device__ __forceinline__ float f_ref(float rho, float jx, float jy, int cx, int cy) {
+    return __builtin_fmaf(3.f, (float)cx * jx + (float)cy * jy, rho);
+}
+
+// reference planes: U, rho, jx, jy (the last three with flow only)
+enum { R_U = 0, R_RHO = 1, R_JX = 2, R_JY = 3 };
 
 // Sum of the eight moving populations in a fixed pairwise order.
 __device__ __forceinline__ float sum8(const float v[9]) {
@@ -132,20 +149,37 @@ __device__ __forceinline__ double load_h(const DomDesc& d, int par, int64_t idx,
     return phi;
 }
 
-// Reference of the 16-bit g_q at (x, y): U(t-1) of the cell it streamed from, with the closure
-// (the inlet ghost carries U_in).
+// Reference values (U, rho, jx, jy) of lattice position (gx, gy) with the closure: the inlet ghost
+// carries (U_in, rho0, rho0 u_in, 0) rounded to the storage format.
 template <class S>
-__device__ __forceinline__ float g_ref(const DomDesc& d, int par, int x, int y, int q) {
-    if (!S::kLocalRef) return 0.f;
-    int gx = x - CX[q];
-    const int gy = wrapi(y - CY[q], d.ny);
+__device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy, float r[4]) {
+    if (!S::kLocalRef) {
+        r[0] = r[1] = r[2] = r[3] = 0.f;
+        return;
+    }
+    const int sy = wrapi(gy, d.ny);
     if (d.inout) {
-        if (gx < 0) return d.U_in;
+        if (gx < 0) {
+            r[R_U] = S::from_ref(S::to_ref(d.U_in));
+            r[R_RHO] = S::from_ref(S::to_ref(d.ref_f));
+            r[R_JX] = S::from_ref(S::to_ref(d.ref_f * d.u_in));
+            r[R_JY] = 0.f;
+            return;
+        }
         if (gx >= d.nx) gx = d.nx - 1;
     } else {
         gx = wrapi(gx, d.nx);
     }
-    return d.uprev[par][(int64_t)gy * d.pitch + gx];
+    const int64_t i = (int64_t)sy * d.pitch + gx;
+    const typename S::T* b = reinterpret_cast<const typename S::T*>(d.refs[par]);
+    r[R_U] = S::from_ref(b[i]);
+    if (d.npop == 23) {
+        r[R_RHO] = S::from_ref(b[d.rplane + i]);
+        r[R_JX] = S::from_ref(b[2 * d.rplane + i]);
+        r[R_JY] = S::from_ref(b[3 * d.rplane + i]);
+    } else {
+        r[R_RHO] = r[R_JX] = r[R_JY] = 0.f;
+    }
 }
 
 // Decode every population of an in-domain cell (non-hot kernels).
@@ -157,13 +191,12 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
 #pragma unroll
     for (int q = 0; q < 9; ++q) h[q] = S::dec(plane_ptr<S>(d, par, d.off_h + q)[i], W9[q], hr);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) g[q] = S::dec(plane_ptr<S>(d, par, d.off_g + q)[i], W5[q], g_ref<S>(d, par, x, y, q));
-    if (flow) {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = S::dec(plane_ptr<S>(d, par, q)[i], W9[q], d.ref_f);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = 0.f;
+    for (int q = 0; q < 9; ++q) {
+        float r[4];
+        ref_at<S>(d, par, x - CX[q], y - CY[q], r);
+        if (q < 5) g[q] = S::dec(plane_ptr<S>(d, par, d.off_g + q)[i], W5[q], r[R_U]);
+        f[q] = flow ? S::dec(plane_ptr<S>(d, par, q)[i], W9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]))
+                    : 0.f;
     }
 }
 
@@ -173,12 +206,13 @@ template <int TX, int TY, class S, bool FLOW, bool INOUT>
 __global__ void __launch_bounds__(TX * TY)
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     constexpr bool REF = S::kLocalRef;
+    constexpr int NR = REF ? (FLOW ? 4 : 1) : 1;  // reference planes staged in LDS
     constexpr int NT = TX * TY;
     constexpr int LX = TX + 2, LY = TY + 2, LN = LX * LY;
     constexpr int RING = 2 * LX + 2 * TY;
     __shared__ double s_phi[LN];
     __shared__ float s_h[9][LN];
-    __shared__ float s_up[REF ? LN : 1];
+    __shared__ float s_ref[NR][REF ? LN : 1];
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
@@ -197,35 +231,50 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         const int x = td.x0 + tx, y = td.y0 + ty;
         const bool active = (x < d.nx) && (y < d.ny);
         const int64_t cidx = (int64_t)y * d.pitch + x;
+        const typename S::T* rbase = REF ? reinterpret_cast<const typename S::T*>(d.refs[par]) : nullptr;
 
         // ---- own cell first (all threads; ragged positions hold wrapped / ghost data): raw loads
-        typename S::T graw[5];
-        float f[9], phip = 0.f;
+        typename S::T graw[5], fraw[9];
+        float phip = 0.f;
         if (active) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) graw[q] = plane_ptr<S>(d, par, d.off_g + q)[cidx];
             if (FLOW) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) f[q] = S::dec(plane_ptr<S>(d, par, q)[cidx], W9[q], d.ref_f);
+                for (int q = 0; q < 9; ++q) fraw[q] = plane_ptr<S>(d, par, q)[cidx];
             }
             phip = d.phip[par][cidx];
         }
-        float h[9];
-        {
-            int64_t oidx;
-            double p64 = -1.0;
-            const bool real = map_pos<INOUT>(d, x, y, oidx);
+        // stage phi, h and (16-bit storage) the reference values of one lattice position
+        auto stage = [&](int gx, int gy, int li, float hh[9]) {
+            int64_t idx;
+            const bool real = map_pos<INOUT>(d, gx, gy, idx);
+            double p64 = -1.0;  // inlet ghost: phi = -1 (its h are never read)
             if (real) {
-                p64 = load_h<S>(d, par, oidx, h);
+                p64 = load_h<S>(d, par, idx, hh);
             } else {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) h[q] = 0.f;
+                for (int q = 0; q < 9; ++q) hh[q] = 0.f;
             }
-            s_phi[own] = p64;
+            s_phi[li] = p64;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) s_h[q][own] = h[q];
-            if (REF) s_up[own] = real ? d.uprev[par][oidx] : d.U_in;
-        }
+            for (int q = 0; q < 9; ++q) s_h[q][li] = hh[q];
+            if (REF) {
+                if (real) {
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) s_ref[k][li] = S::from_ref(rbase[k * d.rplane + idx]);
+                } else {
+                    s_ref[R_U][li] = S::from_ref(S::to_ref(d.U_in));
+                    if (FLOW) {
+                        s_ref[R_RHO][li] = S::from_ref(S::to_ref(d.ref_f));
+                        s_ref[R_JX][li] = S::from_ref(S::to_ref(d.ref_f * d.u_in));
+                        s_ref[R_JY][li] = 0.f;
+                    }
+                }
+            }
+        };
+        float h[9];
+        stage(x, y, own, h);
 
         // ---- halo ring
         for (int r = tid; r < RING; r += NT) {
@@ -234,29 +283,27 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             else if (r < 2 * LX) { lx = r - LX; ly = LY - 1; }
             else if (r < 2 * LX + TY) { lx = 0; ly = 1 + (r - 2 * LX); }
             else { lx = LX - 1; ly = 1 + (r - 2 * LX - TY); }
-            int64_t ridx;
-            const bool real = map_pos<INOUT>(d, td.x0 + lx - 1, td.y0 + ly - 1, ridx);
             float hr[9];
-            double pr = -1.0;  // inlet ghost: phi = -1 (its h are never read)
-            if (real) {
-                pr = load_h<S>(d, par, ridx, hr);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) hr[q] = 0.f;
-            }
-            const int li = ly * LX + lx;
-            s_phi[li] = pr;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s_h[q][li] = hr[q];
-            if (REF) s_up[li] = real ? d.uprev[par][ridx] : d.U_in;
+            stage(td.x0 + lx - 1, td.y0 + ly - 1, ly * LX + lx, hr);
         }
         __syncthreads();
 
         if (active) {
-            // ---- vapour populations and moments
-            float g[5];
+            // ---- vapour and flow populations (16-bit: references of their source cells)
+            float g[5], f[9];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) g[q] = S::dec(graw[q], W5[q], REF ? s_up[own - CY[q] * LX - CX[q]] : 0.f);
+            for (int q = 0; q < 5; ++q) g[q] = S::dec(graw[q], W5[q], REF ? s_ref[R_U][own - CY[q] * LX - CX[q]] : 0.f);
+            if (FLOW) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    float m = 0.f;
+                    if (REF) {
+                        const int ls = own - CY[q] * LX - CX[q];
+                        m = f_ref(s_ref[R_RHO][ls], s_ref[R_JX][ls], s_ref[R_JY][ls], CX[q], CY[q]);
+                    }
+                    f[q] = S::dec(fraw[q], W9[q], m);
+                }
+            }
             const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
 
             // ---- E4 gradient (Table 1: 1/3 on axis neighbours, 1/12 on diagonals, no 1/cs^2), FP64
@@ -307,12 +354,12 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             // rounding is left.
 
             // ---- flow: drag and projection, Guo forcing, 2nd-order equilibrium (Sec. 2.2.1)
-            float ux = 0.f, uy = 0.f;
+            float ux = 0.f, uy = 0.f, rho = 0.f, jx = 0.f, jy = 0.f;
             float fs[9];
             if (FLOW) {
-                const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-                const float jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-                const float jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+                rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+                jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 const float pc = fminf(fmaxf(phi, -1.f), 1.f);
                 const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
                 const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
@@ -363,13 +410,30 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             heq[0] = phi - sum8(heq);
             shq[0] = srcQ - sum8(shq);
 
-            // ---- push streaming into copy 1 - par
+            // ---- references this cell hands to the populations it emits (16-bit storage)
             const int npar = 1 - par;
+            float rU = 0.f, rR = 0.f, rJx = 0.f, rJy = 0.f;
+            if (REF) {
+                typename S::T* wb = reinterpret_cast<typename S::T*>(d.refs[npar]);
+                const typename S::T tU = S::to_ref(U);
+                wb[cidx] = tU;
+                rU = S::from_ref(tU);
+                if (FLOW) {
+                    const typename S::T tR = S::to_ref(rho), tX = S::to_ref(jx), tY = S::to_ref(jy);
+                    wb[d.rplane + cidx] = tR;
+                    wb[2 * d.rplane + cidx] = tX;
+                    wb[3 * d.rplane + cidx] = tY;
+                    rR = S::from_ref(tR);
+                    rJx = S::from_ref(tX);
+                    rJy = S::from_ref(tY);
+                }
+            }
+
+            // ---- push streaming into copy 1 - par
             const int yN = (y + 1 < d.ny) ? y + 1 : 0;
             const int yS = (y > 0) ? y - 1 : d.ny - 1;
             const int xE = (x + 1 < d.nx) ? x + 1 : (INOUT ? -1 : 0);
             const int xW = (x > 0) ? x - 1 : (INOUT ? -1 : d.nx - 1);
-            const float gref = REF ? U : 0.f;  // g references the U of its source (this cell)
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
@@ -377,12 +441,13 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 const float hs = h[q] - (h[q] - heq[q]) * ieta + shq[q];
                 const float Pq = hs * ia2;
                 const int lq = own + CY[q] * LX + CX[q];
+                const float fm = (REF && FLOW) ? f_ref(rR, rJx, rJy, CX[q], CY[q]) : 0.f;
                 if (xd >= 0) {
                     const int64_t di = (int64_t)yd * d.pitch + xd;
                     const float href = REF ? (float)s_phi[lq] : 0.f;  // h references its holder's phi(t)
                     plane_ptr_w<S>(d, npar, d.off_h + q)[di] = S::enc(Pq - B * s_h[q][lq], IW9[q], href);
-                    if (FLOW) plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], d.ref_f);
-                    if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], gref);
+                    if (FLOW) plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], fm);
+                    if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], rU);
                 }
                 if (INOUT) {
                     if (CX[q] < 0 && x == d.nx - 1) {
@@ -391,20 +456,25 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         const int ld = own + CY[q] * LX;
                         const float href = REF ? (float)s_phi[ld] : 0.f;
                         plane_ptr_w<S>(d, npar, d.off_h + q)[di] = S::enc(Pq - B * s_h[q][ld], IW9[q], href);
-                        plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], d.ref_f);
-                        if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], gref);
+                        plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], fm);
+                        if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], rU);
                     }
                     if (CX[q] > 0 && x == 0) {
-                        // inlet ghost at x = -1: equilibrium at (rho0, u_in; U_in; phi = -1)
+                        // inlet ghost at x = -1: equilibrium at (rho0, u_in; U_in; phi = -1); its
+                        // reference values are the LDS ones of the ghost column
+                        const int lg = own - CX[q] - CY[q] * LX;  // the ghost source in the LDS halo
+                        float gfm = 0.f, ggm = 0.f;
+                        if (REF) {
+                            ggm = s_ref[R_U][lg];
+                            gfm = f_ref(s_ref[R_RHO][lg], s_ref[R_JX][lg], s_ref[R_JY][lg], CX[q], CY[q]);
+                        }
                         plane_ptr_w<S>(d, npar, d.off_h + q)[cidx] = S::enc(-W9[q], IW9[q], REF ? phi : 0.f);
-                        plane_ptr_w<S>(d, npar, q)[cidx] = S::enc(d.f_in[q], IW9[q], d.ref_f);
-                        if (q < 5)
-                            plane_ptr_w<S>(d, npar, d.off_g + q)[cidx] = S::enc(d.g_in[q], IW5[q], REF ? d.U_in : 0.f);
+                        plane_ptr_w<S>(d, npar, q)[cidx] = S::enc(d.f_in[q], IW9[q], gfm);
+                        if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[cidx] = S::enc(d.g_in[q], IW5[q], ggm);
                     }
                 }
             }
             d.phip[npar][cidx] = phi;
-            if (REF) d.uprev[npar][cidx] = U;
         }
         __syncthreads();  // LDS is reused by the next tile
     }
@@ -502,33 +572,65 @@ hipError_t launch_step(int cfg, int storage, int flow, int inout, const DomDesc*
 
 // ---------------------------------------------------------------------------------------------
 // initial state: circular tanh seed, equilibrium populations (rest population as remainder)
-__device__ __forceinline__ float init_U(const DomDesc& d, const float* __restrict__ U_init, float U0, int x, int y) {
-    // U at a lattice position with the closure (used for the 16-bit g references)
-    y = wrapi(y, d.ny);
+struct InitArgs {
+    const float* U_init;  // ny x nx or null
+    float U0, sx, sy, R, width, u_in;
+};
+
+// Initial phi, x-velocity and U at an in-domain lattice position.
+__device__ __forceinline__ void init_at(const DomDesc& d, const InitArgs& a, int x, int y, float& phi0, float& ux,
+                                        float& U) {
+    const float dx = (float)x - a.sx, dy = (float)y - a.sy;
+    const float r = sqrtf(dx * dx + dy * dy);
+    phi0 = tanhf((a.R - r) / (1.41421356237309505f * a.width));
+    ux = (d.npop == 23 && d.inout) ? 0.5f * (1.f - phi0) * a.u_in : 0.f;
+    U = a.U_init ? a.U_init[(int64_t)y * d.nx + x] : a.U0;
+}
+
+// Reference values of the initial state at any lattice position, with the closure of ref_at.
+template <class S>
+__device__ __forceinline__ void init_ref_at(const DomDesc& d, const InitArgs& a, int gx, int gy, float r[4]) {
+    const int sy = wrapi(gy, d.ny);
     if (d.inout) {
-        if (x < 0) return d.U_in;
-        if (x >= d.nx) x = d.nx - 1;
+        if (gx < 0) {
+            r[R_U] = S::from_ref(S::to_ref(d.U_in));
+            r[R_RHO] = S::from_ref(S::to_ref(d.ref_f));
+            r[R_JX] = S::from_ref(S::to_ref(d.ref_f * d.u_in));
+            r[R_JY] = 0.f;
+            return;
+        }
+        if (gx >= d.nx) gx = d.nx - 1;
     } else {
-        x = wrapi(x, d.nx);
+        gx = wrapi(gx, d.nx);
     }
-    return U_init ? U_init[(int64_t)y * d.nx + x] : U0;
+    float phi0, ux, U;
+    init_at(d, a, gx, sy, phi0, ux, U);
+    r[R_U] = S::from_ref(S::to_ref(U));
+    r[R_RHO] = S::from_ref(S::to_ref(d.ref_f));
+    r[R_JX] = S::from_ref(S::to_ref(d.ref_f * ux));
+    r[R_JY] = 0.f;
 }
 
 template <class S>
-__global__ void k_init(DomDesc d, int par, const float* __restrict__ U_init, float U0, float sx,
-                       float sy, float R, float width, float rho0, float u_in) {
+__global__ void k_init(DomDesc d, int par, InitArgs a) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx || y >= d.ny) return;
     const bool flow = d.npop == 23;
-    const float dx = (float)x - sx, dy = (float)y - sy;
-    const float r = sqrtf(dx * dx + dy * dy);
-    const float phi0 = tanhf((R - r) / (1.41421356237309505f * width));
-    const float ux = (flow && d.inout) ? 0.5f * (1.f - phi0) * u_in : 0.f;
-    const float U = init_U(d, U_init, U0, x, y);
+    const float rho0 = d.ref_f;
+    float phi0, ux, U;
+    init_at(d, a, x, y, phi0, ux, U);
     const int64_t i = (int64_t)y * d.pitch + x;
     d.phip[par][i] = phi0;
-    if (S::kLocalRef) d.uprev[par][i] = U;
+    if (S::kLocalRef) {
+        typename S::T* wb = reinterpret_cast<typename S::T*>(d.refs[par]);
+        wb[i] = S::to_ref(U);
+        if (flow) {
+            wb[d.rplane + i] = S::to_ref(rho0);
+            wb[2 * d.rplane + i] = S::to_ref(rho0 * ux);
+            wb[3 * d.rplane + i] = S::to_ref(0.f);
+        }
+    }
     float hq[9];
 #pragma unroll
     for (int q = 1; q < 9; ++q) hq[q] = W9[q] * phi0;
@@ -536,43 +638,40 @@ __global__ void k_init(DomDesc d, int par, const float* __restrict__ U_init, flo
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(hq[q], IW9[q], S::kLocalRef ? phi0 : 0.f);
-    if (flow) {
-        const float uu = ux * ux;
-        float fq[9];
+    float fq[9], gq[5];
+    const float uu = ux * ux;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) {
-            const float cu = CX[q] * ux;
-            fq[q] = W9[q] * rho0 * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
-        }
-        fq[0] = rho0 - sum8(fq);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) plane_ptr_w<S>(d, par, q)[i] = S::enc(fq[q], IW9[q], d.ref_f);
+    for (int q = 1; q < 9; ++q) {
+        const float cu = CX[q] * ux;
+        fq[q] = W9[q] * rho0 * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
     }
-    float gq[5];
+    fq[0] = rho0 - sum8(fq);
 #pragma unroll
     for (int q = 1; q < 5; ++q) gq[q] = W5[q] * U * (1.f + 3.f * CX[q] * ux);
     gq[0] = U - ((gq[1] + gq[2]) + (gq[3] + gq[4]));
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        const float ref = S::kLocalRef ? init_U(d, U_init, U0, x - CX[q], y - CY[q]) : 0.f;
-        plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], ref);
+    for (int q = 0; q < 9; ++q) {
+        float r[4] = {0.f, 0.f, 0.f, 0.f};
+        if (S::kLocalRef) init_ref_at<S>(d, a, x - CX[q], y - CY[q], r);
+        if (flow) plane_ptr_w<S>(d, par, q)[i] = S::enc(fq[q], IW9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
+        if (q < 5) plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], r[R_U]);
     }
 }
 
 template <class S>
-static hipError_t init_s(const DomDesc& d, int par, const float* U_init, float U0, float sx, float sy,
-                         float R, float w, float rho0, float u_in, hipStream_t s) {
+static hipError_t init_s(const DomDesc& d, int par, const InitArgs& a, hipStream_t s) {
     dim3 grid((d.nx + 255) / 256, d.ny);
-    hipLaunchKernelGGL(k_init<S>, grid, dim3(256), 0, s, d, par, U_init, U0, sx, sy, R, w, rho0, u_in);
+    hipLaunchKernelGGL(k_init<S>, grid, dim3(256), 0, s, d, par, a);
     return hipGetLastError();
 }
 
 hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float sx, float sy,
-                       float R, float w, float rho0, float u_in, hipStream_t s) {
+                       float R, float w, float u_in, hipStream_t s) {
+    const InitArgs a{U_init, U0, sx, sy, R, w, u_in};
     switch (d.storage) {
-        case 0: return init_s<StoreF32>(d, par, U_init, U0, sx, sy, R, w, rho0, u_in, s);
-        case 1: return init_s<StoreF16>(d, par, U_init, U0, sx, sy, R, w, rho0, u_in, s);
-        case 2: return init_s<StoreBF16>(d, par, U_init, U0, sx, sy, R, w, rho0, u_in, s);
+        case 0: return init_s<StoreF32>(d, par, a, s);
+        case 1: return init_s<StoreF16>(d, par, a, s);
+        case 2: return init_s<StoreBF16>(d, par, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -647,20 +746,35 @@ __global__ void k_pop_get(DomDesc d, int par, int set, float* __restrict__ canon
     for (int q = 0; q < nq; ++q) canon[q * n + c] = v[q];
 }
 
-// Writing a set re-encodes it against the references the step will decode it with.  Writing g
-// resets U_prev to 0 (any consistent reference is valid); writing phi_prev re-encodes h.
+// Writing a set re-encodes it against the references the step will decode it with.  Writing f
+// (resp. g) resets the rho, j (resp. U) reference planes to 0 -- any consistent reference is valid;
+// populations streamed from the inlet ghost keep the ghost's references.  Writing phi_prev
+// re-encodes h.
 template <class S>
 __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__ canon) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx || y >= d.ny) return;
     const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = (int64_t)y * d.pitch + x;
-    if (set == 0) {
-        for (int q = 0; q < 9; ++q) plane_ptr_w<S>(d, par, q)[i] = S::enc(canon[q * n + c], IW9[q], d.ref_f);
+    typename S::T* wb = S::kLocalRef ? reinterpret_cast<typename S::T*>(d.refs[par]) : nullptr;
+    if (set == 0 || set == 1) {
+        if (S::kLocalRef) {
+            if (set == 1) wb[i] = S::to_ref(0.f);
+            else for (int k = 1; k < 4; ++k) wb[k * d.rplane + i] = S::to_ref(0.f);
+        }
+        const int nq = set == 0 ? 9 : 5;
+        for (int q = 0; q < nq; ++q) {
+            float r[4] = {0.f, 0.f, 0.f, 0.f};
+            if (S::kLocalRef && d.inout && x - CX[q] < 0) ref_at<S>(d, par, -1, y - CY[q], r);  // ghost constants
+            if (set == 0)
+                plane_ptr_w<S>(d, par, q)[i] = S::enc(canon[q * n + c], IW9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
+            else
+                plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], r[R_U]);
+        }
     } else if (set == 2) {
         const float ref = S::kLocalRef ? d.phip[par][i] : 0.f;
         for (int q = 0; q < 9; ++q) plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(canon[q * n + c], IW9[q], ref);
-    } else if (set == 3) {
+    } else {
         const float pnew = canon[c];
         if (S::kLocalRef) {
             const float pold = d.phip[par][i];
@@ -670,12 +784,6 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
             }
         }
         d.phip[par][i] = pnew;
-    } else {
-        if (S::kLocalRef) d.uprev[par][i] = 0.f;
-        for (int q = 0; q < 5; ++q) {
-            const float ref = (S::kLocalRef && d.inout && x - CX[q] < 0) ? d.U_in : 0.f;
-            plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], ref);
-        }
     }
 }
 

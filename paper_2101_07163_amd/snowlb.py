@@ -278,7 +278,8 @@ class Sim:
         return self
 
     def set_state(self, f=None, g=None, h=None, phip=None):
-        for name, v in (("f", f), ("g", g), ("h", h), ("phip", phip)):
+        # phi_prev first: with 16-bit storage h is encoded against it
+        for name, v in (("phip", phip), ("f", f), ("g", g), ("h", h)):
             if v is not None:
                 self.write_populations(name, v)
         return self

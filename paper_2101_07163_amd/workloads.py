@@ -80,13 +80,17 @@ def c5_U_init(cfg: dict = C5) -> np.ndarray:
 
 
 def random_state(nx: int, ny: int, seed: int, flow: bool = True, amp: float = 0.02,
-                 n_blobs: int = 3) -> dict:
+                 n_blobs: int = 3, well_conditioned: bool = False) -> dict:
     """A seeded, smooth, arbitrary population state [q, y, x] (float64) for one-step parity tests.
 
     The phase populations are spread around a few smooth blobs (values in [-1, 1]) so that the
     gradient, the anisotropy and the Walsh term are all exercised; flow and vapour populations are
     positive values with small smooth and random parts (the flow base is a fluid near rest).  Any
     state is a legal input of the step; nothing here evaluates the method.
+
+    ``well_conditioned``: the blobs' tails are cut to exactly -1 and the bulk carries no noise, so
+    the phase field is either exactly uniform or has gradients well above rounding level (the
+    direction of a tiny gradient is ill-conditioned, which amplifies input differences of one ulp).
     """
     rng = np.random.default_rng(seed)
     y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
@@ -96,14 +100,18 @@ def random_state(nx: int, ny: int, seed: int, flow: bool = True, amp: float = 0.
         R = rng.uniform(2.0, max(3.0, min(nx, ny) / 4))
         r = np.hypot(x - cx, y - cy)
         s = np.maximum(s, np.tanh((R - r) / math.sqrt(2.0)))
+    bulk = np.zeros_like(s, dtype=bool)
+    if well_conditioned:
+        bulk = s < -1.0 + 1e-3
+        s = np.where(bulk, -1.0, s)
     share9 = rng.uniform(0.5, 1.5, size=9)
     share9 /= share9.sum()
-    h = share9[:, None, None] * s[None] + amp * 0.1 * rng.standard_normal((9, ny, nx))
+    h = share9[:, None, None] * s[None] + np.where(bulk, 0.0, amp * 0.1 * rng.standard_normal((9, ny, nx)))
     U = 0.3 + 0.2 * np.sin(2 * math.pi * x / nx) * np.cos(2 * math.pi * y / ny)
     share5 = rng.uniform(0.5, 1.5, size=5)
     share5 /= share5.sum()
     g = share5[:, None, None] * U[None] * (1 + amp * rng.standard_normal((5, ny, nx)))
-    phip = s + amp * rng.standard_normal((ny, nx))
+    phip = s + np.where(bulk, 0.0, amp * rng.standard_normal((ny, nx)))
     out = {"g": g, "h": h, "phip": phip}
     if flow:
         base = np.array([16, 4, 4, 4, 4, 1, 1, 1, 1], dtype=np.float64) / 36.0
