@@ -101,6 +101,40 @@ def bw_probe(S, torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def batch_sweep(S, torch, W, steps=200, warmup=20, solo_steps=64):
+    """The 64-crystal sweep as one batch (one launch per step over all tiles) against the same work
+    done crystal by crystal (solo contexts, graph-replayed), both in aggregate MLUPS."""
+    cfgs = W.c4_domains()
+    b = S.Batch(cfgs, tile=-1).init()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = b.cells
+    tile = S.snowlb_tile_name(b.tile)
+    del b
+    torch.cuda.empty_cache()
+    solo_ms = 0.0
+    for c in cfgs:
+        sim = S.Sim(c).init()
+        sim.step(8)
+        torch.cuda.synchronize()
+        e0.record()
+        sim.step(solo_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        solo_ms += e0.elapsed_time(e1)
+        del sim
+    return {"domains": len(cfgs), "cells": cells, "steps": steps, "tile": tile,
+            "batched_MLUPS": round(cells * steps / (ms * 1e-3) / 1e6, 1),
+            "solo_sum_MLUPS": round(cells * solo_steps / (solo_ms * 1e-3) / 1e6, 1)}
+
+
 def cpu_baseline(cfg, seconds):
     import oracle
     o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
@@ -129,8 +163,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="copy,fp16,bf16",
-                    help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16")
+    ap.add_argument("--extras", default="copy,fp16,bf16,c4",
+                    help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16, "
+                         "c4 (64-crystal batch)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -206,6 +241,9 @@ def main():
                                          "bytes_per_update": b2}
             log("%s storage: %s" % (st, extras["%s_storage" % st]))
             del s2
+        if "c4" in wanted:
+            extras["c4_batch"] = batch_sweep(S, torch, W)
+            log("64-crystal batch: %s" % extras["c4_batch"])
         out["extras"] = extras
 
     if not args.no_cpu_baseline:

@@ -146,11 +146,43 @@ snowlb_status snowlb_load_state(snowlb_ctx* ctx, const void* buf_dev, int64_t by
 
 /* Step-kernel tile configurations.  snowlb_tile_count() configurations exist; snowlb_tile_name(i)
  * describes one ("64x4" = 64 cells in x by 4 in y per workgroup).  snowlb_set_tile selects one for
- * a context; results are bitwise identical for every configuration. */
+ * a context; results are bitwise identical for every configuration.  Grid modes: 0 = one workgroup
+ * per tile (default), 1 = persistent grid of resident workgroups looping over the tiles. */
 int32_t snowlb_tile_count(void);
 const char* snowlb_tile_name(int32_t i);
 snowlb_status snowlb_set_tile(snowlb_ctx* ctx, int32_t tile);
 int32_t snowlb_get_tile(const snowlb_ctx* ctx);
+snowlb_status snowlb_set_grid_mode(snowlb_ctx* ctx, int32_t grid_mode);
+int32_t snowlb_get_grid_mode(const snowlb_ctx* ctx);
+
+/* ---------------------------------------------------------------------------------------------
+ * Batches: many independent crystals (each its own lattice size and parameters) advanced together,
+ * one launch per step over the tiles of all domains, replayed from a captured HIP graph.  All
+ * domains must share flow, bc_x, storage and n_fold (they select the kernel); everything else may
+ * differ.  Each domain evolves exactly as a context created from the same parameters would
+ * (bitwise: same kernel, same per-domain arithmetic). */
+typedef struct snowlb_batch snowlb_batch;
+
+/* Create a batch of n >= 1 domains from params[0..n-1] (validated like snowlb_create; EINVAL if
+ * they do not share flow, bc_x, storage and n_fold).  *out is NULL on failure. */
+snowlb_status snowlb_batch_create(const snowlb_params* params, int32_t n, snowlb_batch** out);
+void snowlb_batch_destroy(snowlb_batch* b);
+int32_t snowlb_batch_size(const snowlb_batch* b);
+/* Total lattice cells over all domains (-1 for NULL). */
+int64_t snowlb_batch_cells(const snowlb_batch* b);
+/* Initial state of every domain from its own parameters (seed, U0). */
+snowlb_status snowlb_batch_init(snowlb_batch* b, void* stream);
+/* Advance every domain n >= 0 steps (asynchronous).  With tile = -1 in params[0], the first call
+ * autotunes the tile shape and grid mode for the whole batch. */
+snowlb_status snowlb_batch_step(snowlb_batch* b, int32_t n, void* stream);
+int64_t snowlb_batch_step_count(const snowlb_batch* b);
+/* Field / diagnostics of domain i, as snowlb_read / snowlb_diag. */
+snowlb_status snowlb_batch_read(snowlb_batch* b, int32_t i, int32_t field, float* dst_dev, int64_t dst_elems,
+                                void* stream);
+snowlb_status snowlb_batch_diag(snowlb_batch* b, int32_t i, double* out_host, void* stream);
+snowlb_status snowlb_batch_set_tile(snowlb_batch* b, int32_t tile, int32_t grid_mode);
+int32_t snowlb_batch_get_tile(const snowlb_batch* b);
+const char* snowlb_batch_last_error(const snowlb_batch* b);
 
 /* Practical HBM ceiling probe: copy `bytes` (a multiple of 16) from src_dev to dst_dev with a plain
  * coalesced 16-byte-per-lane grid-stride kernel on `stream`.  Used to report measured bandwidth next

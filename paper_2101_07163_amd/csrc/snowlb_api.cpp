@@ -1,18 +1,19 @@
 // snowlb_api.cpp -- host runtime and C ABI of libsnowlb (see include/snowlb.h).
 //
 // Responsibilities: parameter validation (before any HIP call), device allocation of the
-// structure-of-arrays population copies, the step driver (plain launches or replays of a captured
-// HIP graph of K steps), the tile autotuner and its cache, FP64 diagnostics, field read-out and
-// checkpoints.  Every HIP call is checked; errors are returned as status codes with a message.
+// structure-of-arrays population copies, the step driver shared by single contexts and batches
+// (plain launches or replays of a captured HIP graph of K steps over a flat tile list), the tile /
+// grid-mode autotuner and its cache, FP64 diagnostics, field read-out and checkpoints.  Every HIP
+// call is checked; errors are returned as status codes with a message.
 #include <hip/hip_runtime.h>
 #include <sys/stat.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -23,7 +24,7 @@ using namespace snowlb;
 
 namespace {
 
-thread_local std::string g_create_error;
+thread_local std::string g_free_error;  // errors of calls without a context
 
 const double kW9[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 const double kW5[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
@@ -41,61 +42,260 @@ struct StateHeader {
     uint64_t magic;
     int32_t nx, ny, storage, flow;
     int64_t step;
-    int64_t pop_bytes, phip_bytes;
-    uint64_t pad[10];
+    int64_t pop_bytes, phip_bytes, refs_bytes;
+    uint64_t pad[9];
 };
-constexpr uint64_t kMagic = 0x534e4f574c423031ull;  // "SNOWLB01"
+constexpr uint64_t kMagic = 0x534e4f574c423032ull;  // "SNOWLB02"
 static_assert(sizeof(StateHeader) == 128, "header size");
 constexpr int64_t kHeaderBytes = 256;
 
-}  // namespace
+std::string hip_msg(hipError_t e, const char* what) { return std::string(what) + ": " + hipGetErrorString(e); }
+snowlb_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SNOWLB_ENOMEM : SNOWLB_EDEVICE; }
 
-struct snowlb_ctx {
-    snowlb_params p{};
-    int device = 0;
-    int esize = 4;
-    DomDesc dom{};
-    DomDesc* d_dom = nullptr;
-    void* mem = nullptr;  // one allocation: pop[0], pop[1], phip[0], phip[1], refs[0], refs[1]
-    int64_t pop_bytes = 0, phip_bytes = 0, refs_bytes = 0;
-    bool local_ref = false;  // 16-bit storage: reference planes exist
-    double* d_partials = nullptr;
-    double* d_out = nullptr;
-    double* h_out = nullptr;      // pinned, 8 doubles
-    StateHeader* h_hdr = nullptr; // pinned
-    hipStream_t cap_stream = nullptr;
-    // tile configuration and per-configuration tile lists
-    int tile = 0;
+// ---------------------------------------------------------------------------------------------
+// Step driver: a device table of domain descriptors, one flat tile list per tile configuration,
+// the tile configuration and grid mode in use, the ping-pong parity and a captured graph.
+struct Driver {
+    const DomDesc* d_doms = nullptr;  // owned by the caller
+    std::vector<const DomDesc*> h_doms;  // host copies (geometry for the tile lists)
+    int storage = 0, flow = 0, inout = 0;
+    int tile = 0, grid_mode = 0;
     std::vector<TileDesc*> d_tiles;
     std::vector<int> ntiles;
-    // captured step loop
-    hipGraphExec_t gexec = nullptr;
-    int g_steps = 0, g_tile = -1;
     int par = 0;
     int64_t step = 0;
-    bool inited = false;
-    bool tuned = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int g_steps = 0, g_tile = -1, g_mode = -1;
     std::string err;
+
+    ~Driver() { release(); }
+
+    void release() {
+        drop_graph();
+        for (TileDesc*& t : d_tiles)
+            if (t) {
+                (void)hipFree(t);
+                t = nullptr;
+            }
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        cap_stream = nullptr;
+    }
+
+    snowlb_status fail(snowlb_status s, const std::string& m) {
+        err = m;
+        return s;
+    }
+    snowlb_status hipfail(hipError_t e, const char* what) { return fail(hip_status(e), hip_msg(e, what)); }
+
+    snowlb_status setup() {
+        d_tiles.assign(tile_config_count(), nullptr);
+        ntiles.assign(tile_config_count(), 0);
+        hipError_t e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hipfail(e, "hipStreamCreate");
+        return SNOWLB_OK;
+    }
+
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+        g_steps = 0;
+        g_tile = g_mode = -1;
+    }
+
+    snowlb_status ensure_tiles(int cfg) {
+        if (d_tiles[cfg]) return SNOWLB_OK;
+        const int TX = tile_config_tx(cfg), TY = tile_config_ty(cfg);
+        std::vector<TileDesc> t;
+        for (size_t k = 0; k < h_doms.size(); ++k) {
+            const DomDesc& dd = *h_doms[k];
+            const int ntx = (dd.nx + TX - 1) / TX, nty = (dd.ny + TY - 1) / TY;
+            for (int j = 0; j < nty; ++j)
+                for (int i = 0; i < ntx; ++i) t.push_back(TileDesc{(int32_t)k, i * TX, j * TY, 0});
+        }
+        if (t.size() > 0x7fffffff) return fail(SNOWLB_EINVAL, "too many tiles");
+        TileDesc* d = nullptr;
+        hipError_t e = hipMalloc(&d, t.size() * sizeof(TileDesc));
+        if (e != hipSuccess) return hipfail(e, "hipMalloc(tiles)");
+        e = hipMemcpy(d, t.data(), t.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hipfail(e, "hipMemcpy(tiles)");
+        }
+        d_tiles[cfg] = d;
+        ntiles[cfg] = (int)t.size();
+        return SNOWLB_OK;
+    }
+
+    snowlb_status plain(int cfg, int mode, int n, hipStream_t s) {
+        snowlb_status st = ensure_tiles(cfg);
+        if (st) return st;
+        const int grid = step_grid(cfg, ntiles[cfg], storage, flow, inout, mode);
+        for (int i = 0; i < n; ++i) {
+            hipError_t e = launch_step(cfg, storage, flow, inout, d_doms, d_tiles[cfg], ntiles[cfg], grid, par, s);
+            if (e != hipSuccess) return hipfail(e, "step kernel launch");
+            par ^= 1;
+            step += 1;
+        }
+        return SNOWLB_OK;
+    }
+
+    snowlb_status build_graph(int K) {
+        drop_graph();
+        const int grid = step_grid(tile, ntiles[tile], storage, flow, inout, grid_mode);
+        hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hipfail(e, "hipStreamBeginCapture");
+        hipError_t le = hipSuccess;
+        for (int i = 0; i < K && le == hipSuccess; ++i)
+            le = launch_step(tile, storage, flow, inout, d_doms, d_tiles[tile], ntiles[tile], grid, i & 1, cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ee = hipStreamEndCapture(cap_stream, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hipfail(le, "step kernel capture");
+        }
+        if (ee != hipSuccess) return hipfail(ee, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            gexec = nullptr;
+            return hipfail(ie, "hipGraphInstantiate");
+        }
+        g_steps = K;
+        g_tile = tile;
+        g_mode = grid_mode;
+        return SNOWLB_OK;
+    }
+
+    // n steps with the current configuration: whole graphs of K steps (K even, starting from copy
+    // 0) while at least K remain, single launches otherwise.
+    snowlb_status run(int n, hipStream_t s) {
+        snowlb_status st = ensure_tiles(tile);
+        if (st) return st;
+        const int K = std::max(2, env_int("SNOWLB_GRAPH_STEPS", 32) & ~1);
+        if (n < K || env_int("SNOWLB_NO_GRAPH", 0)) return plain(tile, grid_mode, n, s);
+        if (par == 1) {
+            st = plain(tile, grid_mode, 1, s);
+            if (st) return st;
+            n -= 1;
+        }
+        if (n >= K && (!gexec || g_tile != tile || g_mode != grid_mode || g_steps != K)) {
+            st = build_graph(K);
+            if (st) return st;
+        }
+        while (n >= K) {
+            hipError_t e = hipGraphLaunch(gexec, s);
+            if (e != hipSuccess) return hipfail(e, "hipGraphLaunch");
+            step += K;
+            n -= K;
+        }
+        return plain(tile, grid_mode, n, s);
+    }
+
+    // Time every (tile configuration, grid mode) on the current state and keep the fastest: all
+    // candidates first run 2 warm-up steps each (code objects loaded, tile lists built), then each
+    // runs `reps` timed steps three times and its median is kept.  save / restore bracket the
+    // trials, so tuning does not change the simulation.
+    snowlb_status autotune(hipStream_t s, const std::function<snowlb_status()>& save,
+                           const std::function<snowlb_status()>& restore) {
+        snowlb_status st = save();
+        if (st) return st;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            (void)restore();
+            return fail(SNOWLB_EDEVICE, "hipEventCreate");
+        }
+        const int reps = std::max(2, env_int("SNOWLB_TUNE_STEPS", 20) & ~1);
+        int best = 0, best_mode = 0;
+        float best_ms = 1e30f;
+        const int par0 = par;
+        const int64_t step0 = step;
+        for (int cfg = 0; cfg < tile_config_count() && !st; ++cfg)
+            for (int mode = 0; mode < 2 && !st; ++mode) st = plain(cfg, mode, 2, s);
+        for (int cfg = 0; cfg < tile_config_count() && !st; ++cfg)
+            for (int mode = 0; mode < 2 && !st; ++mode) {
+                float t[3];
+                for (int r = 0; r < 3 && !st; ++r) {
+                    (void)hipEventRecord(e0, s);
+                    st = plain(cfg, mode, reps, s);
+                    (void)hipEventRecord(e1, s);
+                    if (st) break;
+                    (void)hipEventSynchronize(e1);
+                    t[r] = 0.f;
+                    (void)hipEventElapsedTime(&t[r], e0, e1);
+                }
+                if (st) break;
+                std::sort(t, t + 3);
+                if (t[1] < best_ms) {
+                    best_ms = t[1];
+                    best = cfg;
+                    best_mode = mode;
+                }
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        par = par0;
+        step = step0;
+        snowlb_status st2 = restore();
+        if (st) return st;
+        if (st2) return st2;
+        tile = best;
+        grid_mode = best_mode;
+        drop_graph();
+        return SNOWLB_OK;
+    }
 };
 
-namespace {
-
-snowlb_status fail(snowlb_ctx* c, snowlb_status s, const std::string& msg) {
-    if (c) c->err = msg;
-    else g_create_error = msg;
-    return s;
+std::string tune_cache_path() {
+    const char* e = std::getenv("SNOWLB_TUNE_CACHE");
+    if (e && *e) return e;
+    const char* h = std::getenv("HOME");
+    return std::string(h ? h : "/tmp") + "/.cache/snowlb_tune.txt";
 }
 
-snowlb_status hip_fail(snowlb_ctx* c, hipError_t e, const char* what) {
-    std::string m = std::string(what) + ": " + hipGetErrorString(e);
-    return fail(c, e == hipErrorOutOfMemory ? SNOWLB_ENOMEM : SNOWLB_EDEVICE, m);
+// Cache lines: "<key> <tile> <grid_mode>" where key is "nx ny storage flow bc" for one lattice and
+// "batch <ndomains> <cells> storage flow bc" for a batch.  The last matching line wins.
+bool tune_lookup(const std::string& key, int& tile, int& mode) {
+    FILE* f = std::fopen(tune_cache_path().c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+        const size_t b = l.find_last_of(' ');
+        if (b == std::string::npos) continue;
+        const size_t a = l.find_last_of(' ', b - 1);
+        if (a == std::string::npos) continue;
+        if (l.substr(0, a) != key) continue;
+        const int t = std::atoi(l.substr(a + 1, b - a - 1).c_str());
+        const int m = std::atoi(l.substr(b + 1).c_str());
+        if (t >= 0 && t < tile_config_count() && (m == 0 || m == 1)) {
+            tile = t;
+            mode = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
 }
 
-#define HIPCHK(c, call)                                       \
-    do {                                                      \
-        hipError_t e_ = (call);                               \
-        if (e_ != hipSuccess) return hip_fail((c), e_, #call); \
-    } while (0)
+void tune_store(const std::string& key, int tile, int mode) {
+    const std::string path = tune_cache_path();
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);  // best effort
+    FILE* f = std::fopen(path.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d\n", key.c_str(), tile, mode);
+    std::fclose(f);
+}
+
+std::string tune_key(const snowlb_params& p) {
+    char b[128];
+    std::snprintf(b, sizeof b, "%d %d %d %d %d", p.nx, p.ny, p.storage, p.flow, p.bc_x);
+    return b;
+}
 
 bool finite_all(const snowlb_params* p) {
     const double v[] = {p->eps, p->W0, p->tau0, p->lambda, p->L_sat, p->tau_vap, p->tau_f, p->h_drag,
@@ -129,6 +329,52 @@ const char* validate_msg(const snowlb_params* p) {
     if (p->diag_every < 0) return "diag_every must be >= 0";
     if (p->tile < -1 || p->tile >= tile_config_count()) return "unknown tile configuration";
     return nullptr;
+}
+
+}  // namespace
+
+// =================================================================================================
+// contexts
+
+struct snowlb_ctx {
+    snowlb_params p{};
+    int esize = 4;
+    DomDesc dom{};
+    DomDesc* d_dom = nullptr;
+    void* mem = nullptr;  // one allocation: pop[0], pop[1], phip[0], phip[1], refs[0], refs[1]
+    int64_t pop_bytes = 0, phip_bytes = 0, refs_bytes = 0;
+    bool local_ref = false;  // 16-bit storage: reference planes exist
+    double* d_partials = nullptr;
+    double* d_out = nullptr;
+    double* h_out = nullptr;       // pinned, 8 doubles
+    StateHeader* h_hdr = nullptr;  // pinned
+    Driver drv;
+    bool inited = false;
+    bool tuned = false;
+    std::string err;
+};
+
+namespace {
+
+snowlb_status fail(snowlb_ctx* c, snowlb_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_free_error = msg;
+    return s;
+}
+
+snowlb_status hip_fail(snowlb_ctx* c, hipError_t e, const char* what) {
+    return fail(c, hip_status(e), hip_msg(e, what));
+}
+
+#define HIPCHK(c, call)                                         \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return hip_fail((c), e_, #call);  \
+    } while (0)
+
+snowlb_status from_driver(snowlb_ctx* c, snowlb_status s) {
+    if (s) c->err = c->drv.err;
+    return s;
 }
 
 void fill_dom(snowlb_ctx* c) {
@@ -166,182 +412,146 @@ void fill_dom(snowlb_ctx* c) {
     for (int q = 0; q < 5; ++q) d.g_in[q] = (float)(kW5[q] * p.U_in * (1.0 + 3.0 * kCX[q] * u));
 }
 
-void drop_graph(snowlb_ctx* c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
-    c->g_steps = 0;
-    c->g_tile = -1;
-}
-
-snowlb_status ensure_tiles(snowlb_ctx* c, int cfg) {
-    if (c->d_tiles[cfg]) return SNOWLB_OK;
-    const int TX = tile_config_tx(cfg), TY = tile_config_ty(cfg);
-    const int ntx = (c->p.nx + TX - 1) / TX, nty = (c->p.ny + TY - 1) / TY;
-    std::vector<TileDesc> t;
-    t.reserve((size_t)ntx * nty);
-    for (int j = 0; j < nty; ++j)
-        for (int i = 0; i < ntx; ++i) t.push_back(TileDesc{0, i * TX, j * TY, 0});
-    TileDesc* d = nullptr;
-    HIPCHK(c, hipMalloc(&d, t.size() * sizeof(TileDesc)));
-    hipError_t e = hipMemcpy(d, t.data(), t.size() * sizeof(TileDesc), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(d);
-        return hip_fail(c, e, "hipMemcpy(tiles)");
+// Allocate and describe one lattice (shared by contexts and batch members).
+snowlb_status ctx_alloc(snowlb_ctx* c) {
+    const snowlb_params* p = &c->p;
+    c->esize = p->storage == SNOWLB_STORE_FP32 ? 4 : 2;
+    fill_dom(c);
+    // geometry: rows 256-byte aligned; planes padded to 64 KiB then staggered by 9 x 256 B
+    const int64_t stagger = env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
+    const int64_t row_align = 256 / c->esize;
+    const int64_t pitch = round_up(p->nx, row_align);
+    const int64_t plane_bytes = round_up(pitch * p->ny * c->esize, 65536) + stagger;
+    c->dom.pitch = (int32_t)pitch;
+    c->dom.plane = plane_bytes / c->esize;
+    c->pop_bytes = round_up(plane_bytes * c->dom.npop, 65536);
+    c->phip_bytes = round_up(pitch * p->ny * 4, 65536) + stagger;
+    c->local_ref = p->storage != SNOWLB_STORE_FP32;
+    int64_t rplane_bytes = 0;
+    if (c->local_ref) {
+        rplane_bytes = round_up(pitch * p->ny * c->esize, 65536) + stagger;
+        c->refs_bytes = round_up(rplane_bytes * (p->flow ? 4 : 1), 65536);
     }
-    c->d_tiles[cfg] = d;
-    c->ntiles[cfg] = (int)t.size();
+    const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
+    HIPCHK(c, hipMalloc(&c->mem, (size_t)total));
+    // zero everything once: the 16-bit encodings reference phi_prev and the reference planes, which
+    // must be defined even before the caller writes them
+    HIPCHK(c, hipMemset(c->mem, 0, (size_t)total));
+    char* base = (char*)c->mem;
+    c->dom.pop[0] = base;
+    c->dom.pop[1] = base + c->pop_bytes;
+    c->dom.phip[0] = (float*)(base + 2 * c->pop_bytes);
+    c->dom.phip[1] = (float*)(base + 2 * c->pop_bytes + c->phip_bytes);
+    c->dom.refs[0] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes : nullptr;
+    c->dom.refs[1] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes + c->refs_bytes : nullptr;
+    c->dom.rplane = rplane_bytes / c->esize;
+    HIPCHK(c, hipMalloc(&c->d_dom, sizeof(DomDesc)));
+    HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMalloc(&c->d_partials, (size_t)diag_blocks(c->dom) * 8 * sizeof(double)));
+    HIPCHK(c, hipMalloc(&c->d_out, 8 * sizeof(double)));
+    HIPCHK(c, hipHostMalloc(&c->h_out, 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(c, hipHostMalloc(&c->h_hdr, sizeof(StateHeader), hipHostMallocDefault));
     return SNOWLB_OK;
 }
 
-snowlb_status launch_steps_plain(snowlb_ctx* c, int cfg, int n, hipStream_t s) {
-    const int grid = step_grid(cfg, c->ntiles[cfg], c->p.storage, c->p.flow, c->p.bc_x);
-    for (int i = 0; i < n; ++i) {
-        hipError_t e = launch_step(cfg, c->p.storage, c->p.flow, c->p.bc_x, c->d_dom, c->d_tiles[cfg],
-                                   c->ntiles[cfg], grid, c->par, s);
-        if (e != hipSuccess) return hip_fail(c, e, "step kernel launch");
-        c->par ^= 1;
-        c->step += 1;
-    }
+void ctx_free(snowlb_ctx* c) {
+    c->drv.release();
+    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->d_out) (void)hipFree(c->d_out);
+    if (c->d_partials) (void)hipFree(c->d_partials);
+    if (c->d_dom) (void)hipFree(c->d_dom);
+    if (c->mem) (void)hipFree(c->mem);
+    c->h_hdr = nullptr;
+    c->h_out = nullptr;
+    c->d_out = c->d_partials = nullptr;
+    c->d_dom = nullptr;
+    c->mem = nullptr;
+}
+
+snowlb_status ctx_init(snowlb_ctx* c, const float* U_init, hipStream_t s) {
+    const snowlb_params& p = c->p;
+    c->drv.par = 0;
+    hipError_t e = launch_init(c->dom, 0, U_init, (float)p.U0, (float)p.seed_x, (float)p.seed_y, (float)p.seed_r,
+                               (float)p.init_width, (float)p.u_in, s);
+    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
+    c->drv.step = 0;
+    c->inited = true;
     return SNOWLB_OK;
 }
 
-snowlb_status build_graph(snowlb_ctx* c, int cfg, int K) {
-    drop_graph(c);
-    const int grid = step_grid(cfg, c->ntiles[cfg], c->p.storage, c->p.flow, c->p.bc_x);
-    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = hipSuccess;
-    for (int i = 0; i < K && le == hipSuccess; ++i)
-        le = launch_step(cfg, c->p.storage, c->p.flow, c->p.bc_x, c->d_dom, c->d_tiles[cfg], c->ntiles[cfg],
-                         grid, i & 1, c->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t ee = hipStreamEndCapture(c->cap_stream, &g);
-    if (le != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return hip_fail(c, le, "step kernel capture");
-    }
-    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
-    hipError_t ie = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) {
-        c->gexec = nullptr;
-        return hip_fail(c, ie, "hipGraphInstantiate");
-    }
-    c->g_steps = K;
-    c->g_tile = cfg;
+snowlb_status ctx_diag(snowlb_ctx* c, int par, double* out, hipStream_t s) {
+    hipError_t e = launch_diag(c->dom, par, c->d_partials, c->d_out, s);
+    if (e != hipSuccess) return hip_fail(c, e, "diag kernels");
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    std::memcpy(out, c->h_out, 8 * sizeof(double));
+    if (out[7] > 0) return fail(c, SNOWLB_ENONFINITE, "non-finite populations found");
     return SNOWLB_OK;
 }
 
-// Run n steps with the current tile configuration: whole graphs of K steps (K even, starting from
-// copy 0) while at least K remain, single launches otherwise.
-snowlb_status run_steps(snowlb_ctx* c, int n, hipStream_t s) {
-    const int cfg = c->tile;
-    snowlb_status st = ensure_tiles(c, cfg);
-    if (st) return st;
-    const int K = std::max(2, env_int("SNOWLB_GRAPH_STEPS", 32) & ~1);
-    if (n < K || env_int("SNOWLB_NO_GRAPH", 0)) return launch_steps_plain(c, cfg, n, s);
-    if (c->par == 1) {
-        st = launch_steps_plain(c, cfg, 1, s);
-        if (st) return st;
-        n -= 1;
-    }
-    if (n >= K && (!c->gexec || c->g_tile != cfg || c->g_steps != K)) {
-        st = build_graph(c, cfg, K);
-        if (st) return st;
-    }
-    while (n >= K) {
-        HIPCHK(c, hipGraphLaunch(c->gexec, s));
-        c->step += K;
-        n -= K;
-    }
-    return launch_steps_plain(c, cfg, n, s);
-}
-
-std::string tune_cache_path() {
-    const char* e = std::getenv("SNOWLB_TUNE_CACHE");
-    if (e && *e) return e;
-    const char* h = std::getenv("HOME");
-    return std::string(h ? h : "/tmp") + "/.cache/snowlb_tune.txt";
-}
-
-std::string tune_key(const snowlb_params& p) {
-    char b[128];
-    std::snprintf(b, sizeof b, "%d %d %d %d %d", p.nx, p.ny, p.storage, p.flow, p.bc_x);
-    return b;
-}
-
-int tune_lookup(const snowlb_params& p) {
-    FILE* f = std::fopen(tune_cache_path().c_str(), "r");
-    if (!f) return -1;
-    const std::string key = tune_key(p);
-    char line[256];
-    int found = -1;
-    while (std::fgets(line, sizeof line, f)) {
-        int nx, ny, st, fl, bc, cfg;
-        if (std::sscanf(line, "%d %d %d %d %d %d", &nx, &ny, &st, &fl, &bc, &cfg) == 6) {
-            char k[128];
-            std::snprintf(k, sizeof k, "%d %d %d %d %d", nx, ny, st, fl, bc);
-            if (key == k && cfg >= 0 && cfg < tile_config_count()) found = cfg;  // last entry wins
-        }
-    }
-    std::fclose(f);
-    return found;
-}
-
-void tune_store(const snowlb_params& p, int cfg) {
-    const std::string path = tune_cache_path();
-    const size_t slash = path.find_last_of('/');
-    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);  // best effort
-    FILE* f = std::fopen(path.c_str(), "a");
-    if (!f) return;
-    std::fprintf(f, "%s %d\n", tune_key(p).c_str(), cfg);
-    std::fclose(f);
-}
-
-// Time every tile configuration on a copy of the current state and keep the fastest.  The state is
-// saved before and restored after, so tuning does not change the simulation.
-snowlb_status autotune(snowlb_ctx* c, hipStream_t s) {
-    const int64_t bytes = snowlb_state_bytes(c);
-    void* save = nullptr;
-    HIPCHK(c, hipMalloc(&save, (size_t)bytes));
-    snowlb_status st = snowlb_save_state(c, save, bytes, s);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int best = 0;
-    float best_ms = 1e30f;
-    const int reps = std::max(2, env_int("SNOWLB_TUNE_STEPS", 10) & ~1);
-    if (!st && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
-        for (int cfg = 0; cfg < tile_config_count() && !st; ++cfg) {
-            st = ensure_tiles(c, cfg);
-            if (st) break;
-            st = launch_steps_plain(c, cfg, 2, s);
-            if (st) break;
-            (void)hipEventRecord(e0, s);
-            st = launch_steps_plain(c, cfg, reps, s);
-            (void)hipEventRecord(e1, s);
-            if (st) break;
-            (void)hipEventSynchronize(e1);
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = cfg;
-            }
-        }
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    snowlb_status st2 = snowlb_load_state(c, save, bytes, s);
-    (void)hipStreamSynchronize(s);
-    (void)hipFree(save);
-    if (st) return st;
-    if (st2) return st2;
-    c->tile = best;
-    c->tuned = true;
-    drop_graph(c);
-    tune_store(c->p, best);
+snowlb_status ctx_save(snowlb_ctx* c, int par, int64_t step, void* buf, hipStream_t s) {
+    HIPCHK(c, hipStreamSynchronize(s));  // the pinned header is reused by the next call
+    StateHeader* h = c->h_hdr;
+    std::memset(h, 0, sizeof *h);
+    h->magic = kMagic;
+    h->nx = c->p.nx;
+    h->ny = c->p.ny;
+    h->storage = c->p.storage;
+    h->flow = c->p.flow;
+    h->step = step;
+    h->pop_bytes = c->pop_bytes;
+    h->phip_bytes = c->phip_bytes;
+    h->refs_bytes = c->refs_bytes;
+    char* b = (char*)buf;
+    HIPCHK(c, hipMemcpyAsync(b, h, sizeof *h, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes, c->dom.pop[par], c->pop_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes, c->dom.phip[par], c->phip_bytes,
+                             hipMemcpyDeviceToDevice, s));
+    if (c->local_ref)
+        HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->dom.refs[par], c->refs_bytes,
+                                 hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     return SNOWLB_OK;
 }
+
+// Load a saved state into copy 0; returns its step count through *step.
+snowlb_status ctx_load(snowlb_ctx* c, const void* buf, int64_t* step, hipStream_t s) {
+    const char* b = (const char*)buf;
+    HIPCHK(c, hipMemcpyAsync(c->h_hdr, b, sizeof(StateHeader), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const StateHeader* h = c->h_hdr;
+    if (h->magic != kMagic || h->nx != c->p.nx || h->ny != c->p.ny || h->storage != c->p.storage ||
+        h->flow != c->p.flow || h->pop_bytes != c->pop_bytes || h->phip_bytes != c->phip_bytes ||
+        h->refs_bytes != c->refs_bytes)
+        return fail(c, SNOWLB_EINVAL, "state buffer does not match this context");
+    HIPCHK(c, hipMemcpyAsync(c->dom.pop[0], b + kHeaderBytes, c->pop_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->dom.phip[0], b + kHeaderBytes + c->pop_bytes, c->phip_bytes,
+                             hipMemcpyDeviceToDevice, s));
+    if (c->local_ref)
+        HIPCHK(c, hipMemcpyAsync(c->dom.refs[0], b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->refs_bytes,
+                                 hipMemcpyDeviceToDevice, s));
+    *step = h->step;
+    return SNOWLB_OK;
+}
+
+int64_t ctx_state_bytes(const snowlb_ctx* c) { return kHeaderBytes + c->pop_bytes + c->phip_bytes + c->refs_bytes; }
 
 }  // namespace
+
+// =================================================================================================
+// batches
+
+struct snowlb_batch {
+    std::vector<snowlb_ctx*> doms;
+    DomDesc* d_doms = nullptr;
+    Driver drv;
+    int64_t cells = 0;
+    bool inited = false;
+    bool tuned = false;
+    bool autotune = false;
+    std::string err;
+};
 
 // =================================================================================================
 extern "C" {
@@ -396,7 +606,7 @@ const char* snowlb_status_str(snowlb_status s) {
     return "SNOWLB_UNKNOWN";
 }
 
-const char* snowlb_last_error(const snowlb_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+const char* snowlb_last_error(const snowlb_ctx* c) { return c ? c->err.c_str() : g_free_error.c_str(); }
 
 snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out) {
     if (!out) return fail(nullptr, SNOWLB_EINVAL, "out is NULL");
@@ -405,73 +615,22 @@ snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out) {
     snowlb_ctx* c = new (std::nothrow) snowlb_ctx();
     if (!c) return fail(nullptr, SNOWLB_ENOMEM, "host allocation failed");
     c->p = *p;
-    c->esize = p->storage == SNOWLB_STORE_FP32 ? 4 : 2;
-    c->d_tiles.assign(tile_config_count(), nullptr);
-    c->ntiles.assign(tile_config_count(), 0);
-    fill_dom(c);
-
-    auto bail = [&](snowlb_status s) {
-        g_create_error = c->err;
+    snowlb_status st = ctx_alloc(c);
+    if (!st) {
+        c->drv.h_doms = {&c->dom};
+        c->drv.d_doms = c->d_dom;
+        c->drv.storage = p->storage;
+        c->drv.flow = p->flow;
+        c->drv.inout = p->bc_x;
+        st = from_driver(c, c->drv.setup());
+    }
+    if (st) {
+        g_free_error = c->err;
         snowlb_destroy(c);
-        return s;
-    };
-    hipError_t e = hipGetDevice(&c->device);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipGetDevice"));
-
-    // geometry: rows 256-byte aligned; planes padded to 64 KiB then staggered by 9 x 256 B
-    const int64_t row_align = 256 / c->esize;
-    const int64_t pitch = round_up(p->nx, row_align);
-    const int64_t plane_bytes =
-        round_up(pitch * p->ny * c->esize, 65536) + env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
-    c->dom.pitch = (int32_t)pitch;
-    c->dom.plane = plane_bytes / c->esize;
-    c->pop_bytes = round_up(plane_bytes * c->dom.npop, 65536);
-    c->phip_bytes = round_up(pitch * p->ny * 4, 65536) + env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
-    c->local_ref = p->storage != SNOWLB_STORE_FP32;
-    int64_t rplane_bytes = 0;
-    if (c->local_ref) {
-        rplane_bytes = round_up(pitch * p->ny * c->esize, 65536) + env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
-        c->refs_bytes = round_up(rplane_bytes * (p->flow ? 4 : 1), 65536);
+        return st;
     }
-    const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
-    e = hipMalloc(&c->mem, (size_t)total);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(state)"));
-    // zero everything once: the 16-bit encodings reference phi_prev and the reference planes, which
-    // must be defined even before the caller writes them
-    e = hipMemset(c->mem, 0, (size_t)total);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMemset(state)"));
-    char* base = (char*)c->mem;
-    c->dom.pop[0] = base;
-    c->dom.pop[1] = base + c->pop_bytes;
-    c->dom.phip[0] = (float*)(base + 2 * c->pop_bytes);
-    c->dom.phip[1] = (float*)(base + 2 * c->pop_bytes + c->phip_bytes);
-    c->dom.refs[0] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes : nullptr;
-    c->dom.refs[1] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes + c->refs_bytes : nullptr;
-    c->dom.rplane = rplane_bytes / c->esize;
-
-    e = hipMalloc(&c->d_dom, sizeof(DomDesc));
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(desc)"));
-    e = hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMemcpy(desc)"));
-    e = hipMalloc(&c->d_partials, (size_t)diag_blocks(c->dom) * 8 * sizeof(double));
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(partials)"));
-    e = hipMalloc(&c->d_out, 8 * sizeof(double));
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipMalloc(out)"));
-    e = hipHostMalloc(&c->h_out, 8 * sizeof(double), hipHostMallocDefault);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipHostMalloc(out)"));
-    e = hipHostMalloc(&c->h_hdr, sizeof(StateHeader), hipHostMallocDefault);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipHostMalloc(header)"));
-    e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return bail(hip_fail(c, e, "hipStreamCreate"));
-
-    c->tile = p->tile >= 0 ? p->tile : 0;
-    if (p->tile == -1) {
-        const int cached = tune_lookup(*p);
-        if (cached >= 0) {
-            c->tile = cached;
-            c->tuned = true;
-        }
-    }
+    c->drv.tile = p->tile >= 0 ? p->tile : 0;
+    if (p->tile == -1 && tune_lookup(tune_key(*p), c->drv.tile, c->drv.grid_mode)) c->tuned = true;
     *out = c;
     return SNOWLB_OK;
 }
@@ -479,29 +638,13 @@ snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out) {
 void snowlb_destroy(snowlb_ctx* c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    drop_graph(c);
-    for (TileDesc* t : c->d_tiles)
-        if (t) (void)hipFree(t);
-    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->h_hdr) (void)hipHostFree(c->h_hdr);
-    if (c->h_out) (void)hipHostFree(c->h_out);
-    if (c->d_out) (void)hipFree(c->d_out);
-    if (c->d_partials) (void)hipFree(c->d_partials);
-    if (c->d_dom) (void)hipFree(c->d_dom);
-    if (c->mem) (void)hipFree(c->mem);
+    ctx_free(c);
     delete c;
 }
 
 snowlb_status snowlb_init(snowlb_ctx* c, const float* U_init_dev, void* stream) {
     if (!c) return SNOWLB_EINVAL;
-    const snowlb_params& p = c->p;
-    c->par = 0;
-    hipError_t e = launch_init(c->dom, 0, U_init_dev, (float)p.U0, (float)p.seed_x, (float)p.seed_y,
-                               (float)p.seed_r, (float)p.init_width, (float)p.u_in, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(c, e, "init kernel");
-    c->step = 0;
-    c->inited = true;
-    return SNOWLB_OK;
+    return ctx_init(c, U_init_dev, (hipStream_t)stream);
 }
 
 snowlb_status snowlb_step(snowlb_ctx* c, int32_t n, void* stream) {
@@ -510,30 +653,47 @@ snowlb_status snowlb_step(snowlb_ctx* c, int32_t n, void* stream) {
     if (!c->inited) return fail(c, SNOWLB_ESTATE, "step before init");
     hipStream_t s = (hipStream_t)stream;
     if (c->p.tile == -1 && !c->tuned && n > 0) {
-        snowlb_status st = autotune(c, s);
-        if (st) return st;
+        void* save = nullptr;
+        const int64_t bytes = ctx_state_bytes(c);
+        HIPCHK(c, hipMalloc(&save, (size_t)bytes));
+        const int par0 = c->drv.par;
+        const int64_t step0 = c->drv.step;
+        snowlb_status st = c->drv.autotune(
+            s, [&] { return ctx_save(c, par0, step0, save, s); },
+            [&] {
+                int64_t st_step = 0;
+                snowlb_status r = ctx_load(c, save, &st_step, s);
+                (void)hipStreamSynchronize(s);
+                c->drv.par = 0;
+                c->drv.step = st_step;
+                return r;
+            });
+        (void)hipFree(save);
+        if (st) return from_driver(c, st);
+        c->tuned = true;
+        tune_store(tune_key(c->p), c->drv.tile, c->drv.grid_mode);
     }
-    if (c->p.diag_every <= 0) return run_steps(c, n, s);
+    if (c->p.diag_every <= 0) return from_driver(c, c->drv.run(n, s));
     while (n > 0) {
         const int k = std::min(n, c->p.diag_every);
-        snowlb_status st = run_steps(c, k, s);
+        snowlb_status st = from_driver(c, c->drv.run(k, s));
         if (st) return st;
         n -= k;
         double out[8];
-        st = snowlb_diag(c, out, stream);
+        st = ctx_diag(c, c->drv.par, out, s);
         if (st) return st;
     }
     return SNOWLB_OK;
 }
 
-int64_t snowlb_step_count(const snowlb_ctx* c) { return c ? c->step : -1; }
+int64_t snowlb_step_count(const snowlb_ctx* c) { return c ? c->drv.step : -1; }
 
 snowlb_status snowlb_read(snowlb_ctx* c, int32_t field, float* dst, int64_t elems, void* stream) {
     if (!c) return SNOWLB_EINVAL;
     if (field < SNOWLB_FIELD_PHI || field > SNOWLB_FIELD_UY) return fail(c, SNOWLB_EINVAL, "unknown field");
     if (!dst || elems < (int64_t)c->p.nx * c->p.ny) return fail(c, SNOWLB_EINVAL, "dst too small");
     if (!c->inited) return fail(c, SNOWLB_ESTATE, "read before init");
-    hipError_t e = launch_read(c->dom, c->par, field, dst, (hipStream_t)stream);
+    hipError_t e = launch_read(c->dom, c->drv.par, field, dst, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "read kernel");
     return SNOWLB_OK;
 }
@@ -545,7 +705,7 @@ snowlb_status snowlb_read_populations(snowlb_ctx* c, int32_t set, float* dst, in
     if (set < SNOWLB_POP_F || set > SNOWLB_POP_PHIP) return fail(c, SNOWLB_EINVAL, "unknown population set");
     if (set == SNOWLB_POP_F && !c->p.flow) return fail(c, SNOWLB_EINVAL, "no flow populations");
     if (!dst || elems < (int64_t)pop_q(set) * c->p.nx * c->p.ny) return fail(c, SNOWLB_EINVAL, "dst too small");
-    hipError_t e = launch_pop_io(c->dom, c->par, set, 1, dst, (hipStream_t)stream);
+    hipError_t e = launch_pop_io(c->dom, c->drv.par, set, 1, dst, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "population read kernel");
     return SNOWLB_OK;
 }
@@ -556,7 +716,7 @@ snowlb_status snowlb_write_populations(snowlb_ctx* c, int32_t set, const float* 
     if (set < SNOWLB_POP_F || set > SNOWLB_POP_PHIP) return fail(c, SNOWLB_EINVAL, "unknown population set");
     if (set == SNOWLB_POP_F && !c->p.flow) return fail(c, SNOWLB_EINVAL, "no flow populations");
     if (!src || elems < (int64_t)pop_q(set) * c->p.nx * c->p.ny) return fail(c, SNOWLB_EINVAL, "src too small");
-    hipError_t e = launch_pop_io(c->dom, c->par, set, 0, const_cast<float*>(src), (hipStream_t)stream);
+    hipError_t e = launch_pop_io(c->dom, c->drv.par, set, 0, const_cast<float*>(src), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(c, e, "population write kernel");
     c->inited = true;
     return SNOWLB_OK;
@@ -565,67 +725,26 @@ snowlb_status snowlb_write_populations(snowlb_ctx* c, int32_t set, const float* 
 snowlb_status snowlb_diag(snowlb_ctx* c, double* out, void* stream) {
     if (!c || !out) return fail(c, SNOWLB_EINVAL, "NULL argument");
     if (!c->inited) return fail(c, SNOWLB_ESTATE, "diag before init");
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_diag(c->dom, c->par, c->d_partials, c->d_out, s);
-    if (e != hipSuccess) return hip_fail(c, e, "diag kernels");
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    std::memcpy(out, c->h_out, 8 * sizeof(double));
-    if (out[7] > 0) return fail(c, SNOWLB_ENONFINITE, "non-finite populations found");
-    return SNOWLB_OK;
+    return ctx_diag(c, c->drv.par, out, (hipStream_t)stream);
 }
 
-int64_t snowlb_state_bytes(const snowlb_ctx* c) {
-    return c ? kHeaderBytes + c->pop_bytes + c->phip_bytes + c->refs_bytes : -1;
-}
+int64_t snowlb_state_bytes(const snowlb_ctx* c) { return c ? ctx_state_bytes(c) : -1; }
 
 snowlb_status snowlb_save_state(snowlb_ctx* c, void* buf, int64_t bytes, void* stream) {
     if (!c || !buf) return fail(c, SNOWLB_EINVAL, "NULL argument");
-    if (bytes < snowlb_state_bytes(c)) return fail(c, SNOWLB_EINVAL, "buffer too small");
+    if (bytes < ctx_state_bytes(c)) return fail(c, SNOWLB_EINVAL, "buffer too small");
     if (!c->inited) return fail(c, SNOWLB_ESTATE, "save before init");
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(c, hipStreamSynchronize(s));  // the pinned header is reused by the next call
-    StateHeader* h = c->h_hdr;
-    std::memset(h, 0, sizeof *h);
-    h->magic = kMagic;
-    h->nx = c->p.nx;
-    h->ny = c->p.ny;
-    h->storage = c->p.storage;
-    h->flow = c->p.flow;
-    h->step = c->step;
-    h->pop_bytes = c->pop_bytes;
-    h->phip_bytes = c->phip_bytes;
-    char* b = (char*)buf;
-    HIPCHK(c, hipMemcpyAsync(b, h, sizeof *h, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes, c->dom.pop[c->par], c->pop_bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes, c->dom.phip[c->par], c->phip_bytes,
-                             hipMemcpyDeviceToDevice, s));
-    if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->dom.refs[c->par],
-                                 c->refs_bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    return SNOWLB_OK;
+    return ctx_save(c, c->drv.par, c->drv.step, buf, (hipStream_t)stream);
 }
 
 snowlb_status snowlb_load_state(snowlb_ctx* c, const void* buf, int64_t bytes, void* stream) {
     if (!c || !buf) return fail(c, SNOWLB_EINVAL, "NULL argument");
-    if (bytes < snowlb_state_bytes(c)) return fail(c, SNOWLB_EINVAL, "buffer too small");
-    hipStream_t s = (hipStream_t)stream;
-    const char* b = (const char*)buf;
-    HIPCHK(c, hipMemcpyAsync(c->h_hdr, b, sizeof(StateHeader), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    const StateHeader* h = c->h_hdr;
-    if (h->magic != kMagic || h->nx != c->p.nx || h->ny != c->p.ny || h->storage != c->p.storage ||
-        h->flow != c->p.flow || h->pop_bytes != c->pop_bytes || h->phip_bytes != c->phip_bytes)
-        return fail(c, SNOWLB_EINVAL, "state buffer does not match this context");
-    HIPCHK(c, hipMemcpyAsync(c->dom.pop[0], b + kHeaderBytes, c->pop_bytes, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(c->dom.phip[0], b + kHeaderBytes + c->pop_bytes, c->phip_bytes,
-                             hipMemcpyDeviceToDevice, s));
-    if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(c->dom.refs[0], b + kHeaderBytes + c->pop_bytes + c->phip_bytes,
-                                 c->refs_bytes, hipMemcpyDeviceToDevice, s));
-    c->par = 0;
-    c->step = h->step;
+    if (bytes < ctx_state_bytes(c)) return fail(c, SNOWLB_EINVAL, "buffer too small");
+    int64_t step = 0;
+    snowlb_status st = ctx_load(c, buf, &step, (hipStream_t)stream);
+    if (st) return st;
+    c->drv.par = 0;
+    c->drv.step = step;
     c->inited = true;
     return SNOWLB_OK;
 }
@@ -636,13 +755,208 @@ const char* snowlb_tile_name(int32_t i) { return tile_config_name(i); }
 snowlb_status snowlb_set_tile(snowlb_ctx* c, int32_t tile) {
     if (!c) return SNOWLB_EINVAL;
     if (tile < 0 || tile >= tile_config_count()) return fail(c, SNOWLB_EINVAL, "unknown tile configuration");
-    c->tile = tile;
+    c->drv.tile = tile;
     c->tuned = true;
-    drop_graph(c);
+    c->drv.drop_graph();
     return SNOWLB_OK;
 }
 
-int32_t snowlb_get_tile(const snowlb_ctx* c) { return c ? c->tile : -1; }
+int32_t snowlb_get_tile(const snowlb_ctx* c) { return c ? c->drv.tile : -1; }
+
+snowlb_status snowlb_set_grid_mode(snowlb_ctx* c, int32_t mode) {
+    if (!c) return SNOWLB_EINVAL;
+    if (mode != 0 && mode != 1) return fail(c, SNOWLB_EINVAL, "grid mode must be 0 or 1");
+    c->drv.grid_mode = mode;
+    c->tuned = true;
+    c->drv.drop_graph();
+    return SNOWLB_OK;
+}
+
+int32_t snowlb_get_grid_mode(const snowlb_ctx* c) { return c ? c->drv.grid_mode : -1; }
+
+// ---------------------------------------------------------------------------------------------- batch
+
+const char* snowlb_batch_last_error(const snowlb_batch* b) { return b ? b->err.c_str() : g_free_error.c_str(); }
+
+void snowlb_batch_destroy(snowlb_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    b->drv.release();
+    if (b->d_doms) (void)hipFree(b->d_doms);
+    for (snowlb_ctx* c : b->doms) snowlb_destroy(c);
+    delete b;
+}
+
+snowlb_status snowlb_batch_create(const snowlb_params* params, int32_t n, snowlb_batch** out) {
+    if (!out) return fail(nullptr, SNOWLB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || n < 1) return fail(nullptr, SNOWLB_EINVAL, "need params and n >= 1");
+    for (int i = 0; i < n; ++i) {
+        if (const char* m = validate_msg(&params[i]))
+            return fail(nullptr, SNOWLB_EINVAL, "domain " + std::to_string(i) + ": " + m);
+        const snowlb_params& a = params[0];
+        const snowlb_params& p = params[i];
+        if (p.flow != a.flow || p.bc_x != a.bc_x || p.storage != a.storage || p.n_fold != a.n_fold)
+            return fail(nullptr, SNOWLB_EINVAL, "batch domains must share flow, bc_x, storage and n_fold");
+    }
+    snowlb_batch* b = new (std::nothrow) snowlb_batch();
+    if (!b) return fail(nullptr, SNOWLB_ENOMEM, "host allocation failed");
+    auto bail = [&](snowlb_status s, const std::string& m) {
+        g_free_error = m;
+        snowlb_batch_destroy(b);
+        return s;
+    };
+    std::vector<DomDesc> h;
+    for (int i = 0; i < n; ++i) {
+        snowlb_ctx* c = nullptr;
+        snowlb_params p = params[i];
+        p.tile = 0;
+        snowlb_status st = snowlb_create(&p, &c);
+        if (st) return bail(st, "domain " + std::to_string(i) + ": " + g_free_error);
+        b->doms.push_back(c);
+        h.push_back(c->dom);
+        b->cells += (int64_t)p.nx * p.ny;
+    }
+    hipError_t e = hipMalloc(&b->d_doms, h.size() * sizeof(DomDesc));
+    if (e != hipSuccess) return bail(hip_status(e), hip_msg(e, "hipMalloc(domains)"));
+    e = hipMemcpy(b->d_doms, h.data(), h.size() * sizeof(DomDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_status(e), hip_msg(e, "hipMemcpy(domains)"));
+    for (snowlb_ctx* c : b->doms) b->drv.h_doms.push_back(&c->dom);
+    b->drv.d_doms = b->d_doms;
+    b->drv.storage = params[0].storage;
+    b->drv.flow = params[0].flow;
+    b->drv.inout = params[0].bc_x;
+    snowlb_status st = b->drv.setup();
+    if (st) return bail(st, b->drv.err);
+    b->drv.tile = params[0].tile >= 0 ? params[0].tile : 0;
+    b->autotune = params[0].tile == -1;
+    *out = b;
+    return SNOWLB_OK;
+}
+
+int32_t snowlb_batch_size(const snowlb_batch* b) { return b ? (int32_t)b->doms.size() : -1; }
+int64_t snowlb_batch_cells(const snowlb_batch* b) { return b ? b->cells : -1; }
+int64_t snowlb_batch_step_count(const snowlb_batch* b) { return b ? b->drv.step : -1; }
+
+snowlb_status snowlb_batch_init(snowlb_batch* b, void* stream) {
+    if (!b) return SNOWLB_EINVAL;
+    for (snowlb_ctx* c : b->doms) {
+        snowlb_status st = ctx_init(c, nullptr, (hipStream_t)stream);
+        if (st) {
+            b->err = c->err;
+            return st;
+        }
+    }
+    b->drv.par = 0;
+    b->drv.step = 0;
+    b->inited = true;
+    return SNOWLB_OK;
+}
+
+static std::string batch_key(const snowlb_batch* b) {
+    const snowlb_params& p = b->doms[0]->p;
+    char k[160];
+    std::snprintf(k, sizeof k, "batch %d %lld %d %d %d", (int)b->doms.size(), (long long)b->cells, p.storage,
+                  p.flow, p.bc_x);
+    return k;
+}
+
+snowlb_status snowlb_batch_step(snowlb_batch* b, int32_t n, void* stream) {
+    if (!b) return SNOWLB_EINVAL;
+    if (n < 0) {
+        b->err = "n must be >= 0";
+        return SNOWLB_EINVAL;
+    }
+    if (!b->inited) {
+        b->err = "step before init";
+        return SNOWLB_ESTATE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (b->autotune && !b->tuned && n > 0) {
+        if (tune_lookup(batch_key(b), b->drv.tile, b->drv.grid_mode)) {
+            b->tuned = true;
+        } else {
+            std::vector<void*> saves(b->doms.size(), nullptr);
+            snowlb_status st = SNOWLB_OK;
+            for (size_t i = 0; i < b->doms.size() && !st; ++i) {
+                hipError_t e = hipMalloc(&saves[i], (size_t)ctx_state_bytes(b->doms[i]));
+                if (e != hipSuccess) {
+                    st = hip_status(e);
+                    b->err = hip_msg(e, "hipMalloc(tune save)");
+                }
+            }
+            const int par0 = b->drv.par;
+            const int64_t step0 = b->drv.step;
+            if (!st)
+                st = b->drv.autotune(
+                    s,
+                    [&] {
+                        for (size_t i = 0; i < b->doms.size(); ++i) {
+                            snowlb_status r = ctx_save(b->doms[i], par0, step0, saves[i], s);
+                            if (r) return r;
+                        }
+                        return SNOWLB_OK;
+                    },
+                    [&] {
+                        int64_t stp = 0;
+                        for (size_t i = 0; i < b->doms.size(); ++i) {
+                            snowlb_status r = ctx_load(b->doms[i], saves[i], &stp, s);
+                            if (r) return r;
+                        }
+                        (void)hipStreamSynchronize(s);
+                        b->drv.par = 0;
+                        b->drv.step = step0;
+                        return SNOWLB_OK;
+                    });
+            for (void* p : saves)
+                if (p) (void)hipFree(p);
+            if (st) {
+                if (b->err.empty()) b->err = b->drv.err;
+                return st;
+            }
+            b->tuned = true;
+            tune_store(batch_key(b), b->drv.tile, b->drv.grid_mode);
+        }
+    }
+    snowlb_status st = b->drv.run(n, s);
+    if (st) b->err = b->drv.err;
+    return st;
+}
+
+snowlb_status snowlb_batch_read(snowlb_batch* b, int32_t i, int32_t field, float* dst, int64_t elems, void* stream) {
+    if (!b || i < 0 || i >= (int32_t)b->doms.size()) return SNOWLB_EINVAL;
+    snowlb_ctx* c = b->doms[i];
+    c->drv.par = b->drv.par;
+    c->drv.step = b->drv.step;
+    snowlb_status st = snowlb_read(c, field, dst, elems, stream);
+    if (st) b->err = c->err;
+    return st;
+}
+
+snowlb_status snowlb_batch_diag(snowlb_batch* b, int32_t i, double* out, void* stream) {
+    if (!b || i < 0 || i >= (int32_t)b->doms.size()) return SNOWLB_EINVAL;
+    snowlb_ctx* c = b->doms[i];
+    c->drv.par = b->drv.par;
+    c->drv.step = b->drv.step;
+    snowlb_status st = snowlb_diag(c, out, stream);
+    if (st) b->err = c->err;
+    return st;
+}
+
+snowlb_status snowlb_batch_set_tile(snowlb_batch* b, int32_t tile, int32_t mode) {
+    if (!b) return SNOWLB_EINVAL;
+    if (tile < 0 || tile >= tile_config_count() || (mode != 0 && mode != 1)) {
+        b->err = "unknown tile configuration or grid mode";
+        return SNOWLB_EINVAL;
+    }
+    b->drv.tile = tile;
+    b->drv.grid_mode = mode;
+    b->tuned = true;
+    b->drv.drop_graph();
+    return SNOWLB_OK;
+}
+
+int32_t snowlb_batch_get_tile(const snowlb_batch* b) { return b ? b->drv.tile : -1; }
 
 snowlb_status snowlb_bw_probe(void* dst, const void* src, int64_t bytes, void* stream) {
     if (!dst || !src || bytes < 0 || bytes % 16) return fail(nullptr, SNOWLB_EINVAL, "bw_probe: bad arguments");

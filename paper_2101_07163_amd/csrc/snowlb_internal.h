@@ -57,8 +57,9 @@ int tile_config_ty(int i);
 // copy 1 - par.  `flow`, `inout`, `storage` must be the same for every domain referenced.
 hipError_t launch_step(int tile_cfg, int storage, int flow, int inout, const DomDesc* doms_dev,
                        const TileDesc* tiles_dev, int ntiles, int grid, int par, hipStream_t s);
-// Persistent grid size used for a launch of `ntiles` tiles with configuration `tile_cfg`.
-int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout);
+// Grid size of a step launch over `ntiles` tiles: grid_mode 0 = one workgroup per tile,
+// 1 = persistent (one wave of resident workgroups looping over the tiles).
+int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout, int grid_mode);
 
 hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float seed_x,
                        float seed_y, float seed_r, float width, float u_in, hipStream_t s);

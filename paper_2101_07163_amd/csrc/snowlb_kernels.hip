@@ -32,7 +32,6 @@
 // reference planes come in two copies, because neighbours read them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
-#include <stdlib.h>
 
 #include "snowlb_internal.h"
 
@@ -532,18 +531,13 @@ static void* step_kernel(int cfg, int storage, int flow, int inout) {
     return nullptr;
 }
 
-static int env_int(const char* name, int def) {
-    const char* v = std::getenv(name);
-    return (v && *v) ? std::atoi(v) : def;
-}
-
-// Grid of a step launch.  Default: one workgroup per tile, dispatched in tile order (measured best
-// for streaming traffic on MI355X).  SNOWLB_GRID_MODE=0 selects a persistent grid of one wave of
-// resident workgroups that loops over the tiles.
-int step_grid(int cfg, int ntiles, int storage, int flow, int inout) {
+// Grid of a step launch.  grid_mode 0: one workgroup per tile, dispatched in (XCD-contiguous) tile
+// order -- measured best for streaming traffic on MI355X.  grid_mode 1: a persistent grid of one
+// wave of resident workgroups that loops over the tiles.
+int step_grid(int cfg, int ntiles, int storage, int flow, int inout, int grid_mode) {
     void* fn = step_kernel(cfg, storage, flow, inout);
     if (!fn || ntiles <= 0) return 0;
-    if (env_int("SNOWLB_GRID_MODE", 1) != 0) return ntiles;
+    if (grid_mode == 0) return ntiles;
     int per_cu = 0;
     const int nt = kTiles[cfg].tx * kTiles[cfg].ty;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), nt, 0) !=
@@ -565,7 +559,7 @@ hipError_t launch_step(int cfg, int storage, int flow, int inout, const DomDesc*
     if (!fn) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
     const int nt = kTiles[cfg].tx * kTiles[cfg].ty;
-    int remap = env_int("SNOWLB_XCD_REMAP", 1);
+    int remap = 1;
     void* args[] = {(void*)&doms_dev, (void*)&tiles_dev, (void*)&ntiles, (void*)&par, (void*)&remap};
     return hipLaunchKernel(fn, dim3(grid), dim3(nt), args, 0, s);
 }

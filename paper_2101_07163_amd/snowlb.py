@@ -70,7 +70,21 @@ _SIGS = {
     "snowlb_tile_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "snowlb_set_tile": (ctypes.c_int32, [_v, ctypes.c_int32]),
     "snowlb_get_tile": (ctypes.c_int32, [_v]),
+    "snowlb_set_grid_mode": (ctypes.c_int32, [_v, ctypes.c_int32]),
+    "snowlb_get_grid_mode": (ctypes.c_int32, [_v]),
     "snowlb_bw_probe": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
+    "snowlb_batch_create": (ctypes.c_int32, [_P(snowlb_params), ctypes.c_int32, _P(_v)]),
+    "snowlb_batch_destroy": (None, [_v]),
+    "snowlb_batch_size": (ctypes.c_int32, [_v]),
+    "snowlb_batch_cells": (ctypes.c_int64, [_v]),
+    "snowlb_batch_init": (ctypes.c_int32, [_v, _v]),
+    "snowlb_batch_step": (ctypes.c_int32, [_v, ctypes.c_int32, _v]),
+    "snowlb_batch_step_count": (ctypes.c_int64, [_v]),
+    "snowlb_batch_read": (ctypes.c_int32, [_v, ctypes.c_int32, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb_batch_diag": (ctypes.c_int32, [_v, ctypes.c_int32, _P(ctypes.c_double), _v]),
+    "snowlb_batch_set_tile": (ctypes.c_int32, [_v, ctypes.c_int32, ctypes.c_int32]),
+    "snowlb_batch_get_tile": (ctypes.c_int32, [_v]),
+    "snowlb_batch_last_error": (ctypes.c_char_p, [_v]),
 }
 
 
@@ -97,9 +111,12 @@ def _status_name(s: int) -> str:
         return "status %d" % s
 
 
-def _check(status: int, ctx=None):
+def _check(status: int, ctx=None, batch=None):
     if status != OK:
-        msg = lib().snowlb_last_error(ctx).decode()
+        if batch is not None:
+            msg = lib().snowlb_batch_last_error(batch).decode()
+        else:
+            msg = lib().snowlb_last_error(ctx).decode()
         raise SnowlbError(status, msg)
 
 
@@ -187,8 +204,67 @@ def snowlb_get_tile(ctx) -> int:
     return int(lib().snowlb_get_tile(ctx))
 
 
+def snowlb_set_grid_mode(ctx, mode: int) -> None:
+    _check(lib().snowlb_set_grid_mode(ctx, mode), ctx)
+
+
+def snowlb_get_grid_mode(ctx) -> int:
+    return int(lib().snowlb_get_grid_mode(ctx))
+
+
 def snowlb_bw_probe(dst_dev: int, src_dev: int, nbytes: int, stream: int) -> None:
     _check(lib().snowlb_bw_probe(dst_dev, src_dev, nbytes, stream), None)
+
+
+def snowlb_batch_create(params: list) -> ctypes.c_void_p:
+    arr = (snowlb_params * len(params))(*params)
+    b = ctypes.c_void_p()
+    _check(lib().snowlb_batch_create(arr, len(params), ctypes.byref(b)), None)
+    return b
+
+
+def snowlb_batch_destroy(b) -> None:
+    lib().snowlb_batch_destroy(b)
+
+
+def snowlb_batch_size(b) -> int:
+    return int(lib().snowlb_batch_size(b))
+
+
+def snowlb_batch_cells(b) -> int:
+    return int(lib().snowlb_batch_cells(b))
+
+
+def snowlb_batch_init(b, stream: int) -> None:
+    _check(lib().snowlb_batch_init(b, stream), batch=b)
+
+
+def snowlb_batch_step(b, n: int, stream: int) -> None:
+    _check(lib().snowlb_batch_step(b, int(n), stream), batch=b)
+
+
+def snowlb_batch_step_count(b) -> int:
+    return int(lib().snowlb_batch_step_count(b))
+
+
+def snowlb_batch_read(b, i: int, field: int, dst_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb_batch_read(b, i, field, dst_dev, elems, stream), batch=b)
+
+
+def snowlb_batch_diag(b, i: int, stream: int) -> tuple[int, list]:
+    out = (ctypes.c_double * 8)()
+    s = lib().snowlb_batch_diag(b, i, out, stream)
+    if s not in (OK, ENONFINITE):
+        _check(s, batch=b)
+    return s, list(out)
+
+
+def snowlb_batch_set_tile(b, tile: int, grid_mode: int) -> None:
+    _check(lib().snowlb_batch_set_tile(b, tile, grid_mode), batch=b)
+
+
+def snowlb_batch_get_tile(b) -> int:
+    return int(lib().snowlb_batch_get_tile(b))
 
 
 # ----------------------------------------------------------------------------- convenience object
@@ -306,6 +382,77 @@ class Sim:
         snowlb_set_tile(self.ctx, tile)
         return self
 
+    def set_grid_mode(self, mode: int):
+        snowlb_set_grid_mode(self.ctx, mode)
+        return self
+
     @property
     def tile(self) -> int:
         return snowlb_get_tile(self.ctx)
+
+    @property
+    def grid_mode(self) -> int:
+        return snowlb_get_grid_mode(self.ctx)
+
+
+class Batch:
+    """Many independent lattices advanced by one launch per step (see snowlb_batch_* in the header)."""
+
+    def __init__(self, cfgs: list, storage: str | int = "fp32", tile: int = 0):
+        import torch
+        self.torch = torch
+        self.params = [c if isinstance(c, snowlb_params) else make_params(c, storage, tile) for c in cfgs]
+        self.b = snowlb_batch_create(self.params)
+
+    def __del__(self):
+        b = getattr(self, "b", None)
+        if b:
+            try:
+                snowlb_batch_destroy(b)
+            except Exception:  # interpreter shutdown
+                pass
+            self.b = None
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    def __len__(self):
+        return snowlb_batch_size(self.b)
+
+    @property
+    def cells(self) -> int:
+        return snowlb_batch_cells(self.b)
+
+    def init(self):
+        snowlb_batch_init(self.b, self.stream)
+        return self
+
+    def step(self, n: int = 1):
+        snowlb_batch_step(self.b, n, self.stream)
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return snowlb_batch_step_count(self.b)
+
+    def read(self, i: int, field: str):
+        p = self.params[i]
+        out = self.torch.empty((p.ny, p.nx), dtype=self.torch.float32, device="cuda")
+        snowlb_batch_read(self.b, i, FIELDS[field], out.data_ptr(), out.numel(), self.stream)
+        return out
+
+    def diag(self, i: int) -> dict:
+        s, v = snowlb_batch_diag(self.b, i, self.stream)
+        keys = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite")
+        d = dict(zip(keys, v))
+        d["status"] = s
+        return d
+
+    def set_tile(self, tile: int, grid_mode: int = 0):
+        snowlb_batch_set_tile(self.b, tile, grid_mode)
+        return self
+
+    @property
+    def tile(self) -> int:
+        return snowlb_batch_get_tile(self.b)

@@ -82,3 +82,18 @@ def test_tile_configurations():
     names = [S.snowlb_tile_name(i) for i in range(n)]
     assert all(re.fullmatch(r"\d+x\d+", s) for s in names)
     assert S.lib().snowlb_tile_name(n).decode() == "?"
+
+
+def test_batch_rejects_mixed_kernels_before_gpu():
+    a = S.snowlb_params_default()
+    b = S.snowlb_params_default()
+    b.flow = 1
+    arr = (S.snowlb_params * 2)(a, b)
+    out = ctypes.c_void_p(7)
+    assert S.lib().snowlb_batch_create(arr, 2, ctypes.byref(out)) == S.EINVAL and not out.value
+    assert "share" in S.lib().snowlb_batch_last_error(None).decode()
+    a.nx = 1
+    arr = (S.snowlb_params * 2)(a, a)
+    assert S.lib().snowlb_batch_create(arr, 2, ctypes.byref(out)) == S.EINVAL
+    assert "domain 0" in S.lib().snowlb_batch_last_error(None).decode()
+    assert S.lib().snowlb_batch_create(arr, 0, ctypes.byref(out)) == S.EINVAL
