@@ -76,6 +76,11 @@ def lib():
         L.orc_aniso.argtypes = [P(OrcParams), d, d, dp, dp, dp]
         L.orc_grad.argtypes = [P(OrcParams), dp, dp, dp]
         L.orc_threads.restype = ctypes.c_int32
+        L.orc_adj_run.restype = d
+        L.orc_adj_run.argtypes = [P(OrcParams), d, d, d, d, dp, dp, ctypes.c_int32, ctypes.c_int32, dp, dp,
+                                  ctypes.c_void_p]
+        L.orc_loss.restype = d
+        L.orc_loss.argtypes = [P(OrcParams), d, d, d, d, dp, dp, ctypes.c_int32, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -227,3 +232,42 @@ def grad(params: Params, phi: np.ndarray):
     P = ctypes.POINTER(ctypes.c_double)
     lib().orc_grad(ctypes.byref(cp), phi.ctypes.data_as(P), gx.ctypes.data_as(P), gy.ctypes.data_as(P))
     return gx, gy
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def adjoint(params: Params, seed, w_init, U_init, phi_target, nsteps, stride=0):
+    """Loss L = sum (phi_T - phi_target)^2 after nsteps (no flow, periodic) and its FP64 discrete
+    adjoint gradients: returns (L, dL/dU_init [ny, nx], dL/deps, phi_T)."""
+    U = np.ascontiguousarray(U_init, dtype=np.float64)
+    T = np.ascontiguousarray(phi_target, dtype=np.float64)
+    assert U.shape == (params.ny, params.nx) and T.shape == U.shape
+    gU = np.zeros_like(U)
+    ge = ctypes.c_double()
+    phiT = np.zeros_like(U)
+    cp = params.c_struct()
+    xs, ys, R = seed
+    L = lib().orc_adj_run(ctypes.byref(cp), xs, ys, R, w_init, _dp(U), _dp(T), int(nsteps), int(stride),
+                          _dp(gU), ctypes.byref(ge), phiT.ctypes.data_as(ctypes.c_void_p))
+    return L, gU, ge.value, phiT
+
+
+def loss(params: Params, seed, w_init, U_init, phi_target, nsteps):
+    U = np.ascontiguousarray(U_init, dtype=np.float64)
+    T = np.ascontiguousarray(phi_target, dtype=np.float64)
+    cp = params.c_struct()
+    xs, ys, R = seed
+    return lib().orc_loss(ctypes.byref(cp), xs, ys, R, w_init, _dp(U), _dp(T), int(nsteps), None)
+
+
+def final_phi(params: Params, seed, w_init, U_init, nsteps):
+    U = np.ascontiguousarray(U_init, dtype=np.float64)
+    T = np.zeros_like(U)
+    out = np.zeros_like(U)
+    cp = params.c_struct()
+    xs, ys, R = seed
+    lib().orc_loss(ctypes.byref(cp), xs, ys, R, w_init, _dp(U), _dp(T), int(nsteps),
+                   out.ctypes.data_as(ctypes.c_void_p))
+    return out

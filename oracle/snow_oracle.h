@@ -71,6 +71,17 @@ void orc_aniso(const orc_params* p, double gx, double gy, double* a, double* Nx,
 /* E4 gradient of phi[y*nx+x] with the boundary ghosts of this parameter set. */
 void orc_grad(const orc_params* p, const double* phi, double* gx, double* gy);
 
+/* Discrete adjoint (no flow, periodic): runs n steps from the seed with the per-cell initial
+ * supersaturation U_init, evaluates L = sum (phi_T - phi_target)^2, and returns L together with
+ * dL/dU_init (ny*nx) and dL/deps, propagated backwards from checkpoints every `stride` steps
+ * (0: ceil(sqrt(n))).  phiT_out (optional) receives phi_T.  NaN on invalid input. */
+double orc_adj_run(const orc_params* p, double xs, double ys, double R, double w_init, const double* U_init,
+                   const double* phi_target, int32_t nsteps, int32_t stride, double* dL_dUinit, double* dL_deps,
+                   double* phiT_out);
+/* The same loss without gradients (for finite differences). */
+double orc_loss(const orc_params* p, double xs, double ys, double R, double w_init, const double* U_init,
+                const double* phi_target, int32_t nsteps, double* phiT_out);
+
 /* Threads the oracle runs on (OpenMP). */
 int32_t orc_threads(void);
 
