@@ -135,6 +135,49 @@ def batch_sweep(S, torch, W, steps=200, warmup=20, solo_steps=64):
             "solo_sum_MLUPS": round(cells * solo_steps / (solo_ms * 1e-3) / 1e6, 1)}
 
 
+def adjoint_ratio(S, torch, W):
+    """The adjoint workload (512^2, no flow, 5000 steps, sqrt(N) checkpoints): time of the forward pass
+    with checkpoints, of the backward pass (recompute + reverse steps), their ratio, and the plain
+    forward for reference."""
+    cfg = dict(W.C5)
+    n = cfg["steps"]
+    sim = S.Sim(cfg)
+    U = torch.from_numpy(W.c5_U_init(cfg)).float().cuda()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    sim.init(U).step(n)  # warm-up (code objects, graph)
+    torch.cuda.synchronize()
+    sim.init(U)
+    e0.record(stream)
+    sim.step(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    sim.init(U)
+    e0.record(stream)
+    S.snowlb_adj_forward(sim.ctx, n, 0, stream.cuda_stream)
+    e1.record(stream)
+    phi = sim.read("phi")
+    seed = (2 * phi).contiguous()
+    dU = torch.empty_like(seed)
+    torch.cuda.synchronize()
+    e1b = torch.cuda.Event(enable_timing=True)
+    e1b.record(stream)
+    S.snowlb_adj_backward(sim.ctx, seed.data_ptr(), dU.data_ptr(), stream.cuda_stream)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    bwd_ms = e1b.elapsed_time(e2)
+    cells = cfg["nx"] * cfg["ny"]
+    return {"workload": cfg["name"], "steps": n, "ckpt_stride": int(-(-n ** 0.5 // 1)),
+            "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
+            "adjoint_forward_ratio": round(bwd_ms / fwd_ms, 3),
+            "plain_forward_ms": round(plain_ms, 2),
+            "plain_forward_MLUPS": round(cells * n / (plain_ms * 1e-3) / 1e6, 1)}
+
+
 def cpu_baseline(cfg, seconds):
     import oracle
     o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
@@ -163,9 +206,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="copy,fp16,bf16,c4",
+    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5",
                     help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16, "
-                         "c4 (64-crystal batch)")
+                         "c4 (64-crystal batch), c5 (adjoint/forward time ratio)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -199,7 +242,7 @@ def main():
 
     traffic = load_traffic(cfg["name"], args.storage)
     out = {
-        "metric": "coupled MLUPS and % HBM roofline at 2048^2",
+        "metric": "coupled MLUPS and % HBM roofline at 2048^2; adjoint/forward time ratio",
         "value": round(mlups, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -244,6 +287,9 @@ def main():
         if "c4" in wanted:
             extras["c4_batch"] = batch_sweep(S, torch, W)
             log("64-crystal batch: %s" % extras["c4_batch"])
+        if "c5" in wanted:
+            extras["c5_adjoint"] = adjoint_ratio(S, torch, W)
+            log("adjoint: %s" % extras["c5_adjoint"])
         out["extras"] = extras
 
     if not args.no_cpu_baseline:

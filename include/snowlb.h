@@ -156,6 +156,23 @@ snowlb_status snowlb_set_grid_mode(snowlb_ctx* ctx, int32_t grid_mode);
 int32_t snowlb_get_grid_mode(const snowlb_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------------------
+ * Discrete adjoint (contexts with flow = 0, periodic x, FP32 storage; EUNSUPPORTED otherwise).
+ *
+ * snowlb_adj_forward runs n >= 1 steps from the current state (normally right after snowlb_init),
+ * keeping a checkpoint of the state every ckpt_stride steps (0: ceil(sqrt(n))); afterwards the
+ * context holds phi_T (read it with snowlb_read).  snowlb_adj_backward then takes dL/dphi_T
+ * (ny x nx device field) for any loss L(phi_T) and returns, by the hand-written reverse of each step
+ * with the states recomputed from the checkpoints: dL/dU_init (ny x nx device field, the gradient
+ * with respect to the initial supersaturation field), dL/deps and dL/dU0 = sum dL/dU_init (host
+ * doubles, reduced in FP64 in a fixed order).  Memory: about (n/stride + stride) state copies.
+ * The backward may be called several times after one forward (different dL/dphi_T). */
+snowlb_status snowlb_adj_forward(snowlb_ctx* ctx, int32_t n_steps, int32_t ckpt_stride, void* stream);
+snowlb_status snowlb_adj_backward(snowlb_ctx* ctx, const float* dL_dphiT_dev, float* dL_dUinit_dev,
+                                  double* dL_deps_host, double* dL_dU0_host, void* stream);
+/* Change the anisotropy strength of a context (0 <= eps < 0.5); takes effect at the next step. */
+snowlb_status snowlb_set_eps(snowlb_ctx* ctx, double eps);
+
+/* ---------------------------------------------------------------------------------------------
  * Batches: many independent crystals (each its own lattice size and parameters) advanced together,
  * one launch per step over the tiles of all domains, replayed from a captured HIP graph.  All
  * domains must share flow, bc_x, storage and n_fold (they select the kernel); everything else may

@@ -1,0 +1,285 @@
+// snowlb_adjoint.hip -- hand-written discrete adjoint of the fused step (no flow, periodic, FP32).
+//
+// For a loss L(phi_T), the adjoint lambda_t = dL/d(state at t) obeys lambda_t = (dF/ds)^T lambda_{t+1}
+// where F is one step of the phase field (Eq. (d)/(e), anisotropy of Sec. 2.1, E4 gradient of
+// Table 1) and the vapour ADR solver (Sec. 2.2.2) with u = 0.  Each reverse step is two gather
+// kernels over the lattice:
+//   k_adj_a (per cell x): recompute the forward quantities of x from the stored state at t (phi with
+//     its halo for the gradient, a, N, eta, Q, h_eq, h*), take lambda_{t+1} of the populations x
+//     emitted (at x + c_q), and form every adjoint that is local to x: lambda_g(x, t) and
+//     lambda_phiprev(x, t) completely, and for the h adjoint the per-cell factors A_h = (1 - 1/eta)/a^2,
+//     B = (1 - a^2)/a^2, the adjoint of the gradient Gbar(x) and the local part of phibar(x); the
+//     explicit dependence on eps is reduced into per-workgroup FP64 partials.
+//   k_adj_b (per cell x): lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x)   [through h*_q(x)]
+//                                           - B(x - c_q) lambda_h,q(x)      [destination term of Eq. (d)]
+//                                           + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)   [phi = sum h]
+// Layout: every field is a pitched FP32 plane with the state's plane stride; the state slot holds g_0..4
+// then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev; the intermediate slot holds A_h, B,
+// Gbar_x, Gbar_y, phibar.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "snowlb_internal.h"
+
+namespace snowlb {
+
+namespace {
+__device__ constexpr int AX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int AY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr float AW9[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.f, 1.f / 9.f,
+                                     1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+__device__ constexpr float AW5[5] = {1.f / 3.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f};
+
+constexpr int ATX = 64, ATY = 4, ANT = ATX * ATY;
+constexpr int ALX = ATX + 2, ALY = ATY + 2, ALN = ALX * ALY;
+
+__device__ __forceinline__ int wrapn(int i, int n) {
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    return i;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+}  // namespace
+
+__global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
+    __shared__ double s_phi[ALN];
+    __shared__ double s_red[ANT / 64];
+    const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
+    const int ntx = (A.nx + ATX - 1) / ATX;
+    const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < A.nx && y < A.ny;
+    const int64_t P = A.plane;
+    const float* hpl = A.st + 5 * P;  // h planes of the state
+
+    // phi(t) of the tile and its halo, summed in FP64 as in the forward step
+    for (int r = tid; r < ALN; r += ANT) {
+        const int lx = r % ALX, ly = r / ALX;
+        const int gx = ((x0 + lx - 1) % A.nx + A.nx) % A.nx, gy = ((y0 + ly - 1) % A.ny + A.ny) % A.ny;
+        const int64_t i = (int64_t)gy * A.pitch + gx;
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) p += (double)hpl[q * P + i];
+        s_phi[r] = p;
+    }
+    __syncthreads();
+
+    double deps = 0.0;
+    if (active) {
+        const int own = (ty + 1) * ALX + tx + 1;
+        const int64_t i = (int64_t)y * A.pitch + x;
+        float h[9], g[5];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) h[q] = hpl[q * P + i];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) g[q] = A.st[q * P + i];
+        const float phi = (float)s_phi[own];
+        const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+
+        // ---- forward recompute (as the step kernel)
+        const double* S = s_phi + own;
+        const double gx64 = (1.0 / 3.0) * (S[1] - S[-1]) + (1.0 / 12.0) * ((S[ALX + 1] - S[ALX - 1]) + (S[-ALX + 1] - S[-ALX - 1]));
+        const double gy64 = (1.0 / 3.0) * (S[ALX] - S[-ALX]) + (1.0 / 12.0) * ((S[ALX + 1] + S[ALX - 1]) - (S[-ALX + 1] + S[-ALX - 1]));
+        const bool on = gx64 * gx64 + gy64 * gy64 > A.grad_eps2;
+        const float gx = (float)gx64, gy = (float)gy64;
+        float a = 1.f, Cn = 0.f, Sn = 0.f, c = 0.f, iG2 = 0.f;
+        if (on) {
+            iG2 = 1.f / (gx * gx + gy * gy);
+            const float X = gx * gx * iG2, Y = gy * gy * iG2, XY = gx * gy * iG2;
+            if (A.n_fold == 6) {
+                Cn = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
+                Sn = XY * (6.f * X * X - 20.f * X * Y + 6.f * Y * Y);
+            } else {
+                Cn = X * X - 6.f * X * Y + Y * Y;
+                Sn = XY * 4.f * (X - Y);
+            }
+            a = 1.f + A.eps * Cn;
+            c = A.coefN * A.eps * a * Sn;
+        }
+        const float Nx = c * gy, Ny = -c * gx;
+        const float a2 = a * a, ia2 = 1.f / a2, B = ia2 - 1.f;
+        const float ie = 1.f / (3.f * A.Dphi * a2 + 0.5f);
+        const float om = 1.f - phi * phi;
+        const float Q = phi - phi * phi * phi + A.lam * U * om * om;
+
+        // ---- reverse of the phase-field collision and push
+        float ia2b = 0.f, Bb = 0.f, ieb = 0.f, Qb = 0.f, phb = 0.f, Nxb = 0.f, Nyb = 0.f;
+        const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
+            const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
+            const int64_t di = (int64_t)yd * A.pitch + xd;
+            const float Pb = A.lin[(5 + q) * P + di];  // lambda_h,q(x + c_q, t + 1)
+            const float hold = hpl[q * P + di];         // h_q(x + c_q, t)
+            const float heq = AW9[q] * (phi - 3.f * (AX[q] * Nx + AY[q] * Ny));
+            const float hs = h[q] - (h[q] - heq) * ie + AW9[q] * Q * A.inv_tau0;
+            Bb -= Pb * hold;
+            ia2b += Pb * hs;
+            const float hsb = Pb * ia2;
+            ieb += hsb * (heq - h[q]);
+            const float heqb = hsb * ie;
+            Qb += hsb * AW9[q] * A.inv_tau0;
+            phb += AW9[q] * heqb;
+            Nxb -= 3.f * AW9[q] * heqb * AX[q];
+            Nyb -= 3.f * AW9[q] * heqb * AY[q];
+        }
+        phb += Qb * (1.f - 3.f * phi * phi - 4.f * A.lam * U * phi * om);
+        float Ub = Qb * A.lam * om * om;
+        ia2b += Bb;
+        const float a2b = -ia2 * ia2 * ia2b + 3.f * A.Dphi * (-ie * ie * ieb);
+        float ab = 2.f * a * a2b;
+        float Gxb = 0.f, Gyb = 0.f;
+        if (on) {
+            const float cb = gy * Nxb - gx * Nyb;  // N = c (gy, -gx)
+            Gxb += -c * Nyb;
+            Gyb += c * Nxb;
+            ab += A.coefN * A.eps * Sn * cb;
+            const float Sb = A.coefN * A.eps * a * cb;
+            deps = (double)(Cn * ab) + (double)(A.coefN * a * Sn * cb);
+            const float Cb = A.eps * ab;
+            const float m = (float)A.n_fold;
+            Gxb += (Cb * m * Sn * gy - Sb * m * Cn * gy) * iG2;
+            Gyb += (-Cb * m * Sn * gx + Sb * m * Cn * gx) * iG2;
+        }
+
+        // ---- reverse of the vapour collision and push
+        const float qd = 0.5f * (1.f - phi);
+        const bool inside = qd > 0.f && qd < 1.f;
+        const float itg = 1.f / (0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
+        float itgb = 0.f, srcb = 0.f, gsb[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
+            const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
+            gsb[q] = A.lin[q * P + (int64_t)yd * A.pitch + xd];
+            itgb -= gsb[q] * (g[q] - AW5[q] * U);
+            Ub += AW5[q] * gsb[q] * itg;
+            srcb -= AW5[q] * gsb[q];
+        }
+        phb += A.half_Lsat * srcb;
+        if (inside) phb += -0.5f * A.tauv_m_half * (-itg * itg * itgb);
+        phb += A.lin[14 * P + i];  // phi_prev(t + 1) = phi(t)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) A.lout[q * P + i] = gsb[q] * (1.f - itg) + Ub;
+        A.lout[14 * P + i] = -A.half_Lsat * srcb;
+        A.mid[0 * P + i] = ia2 * (1.f - ie);
+        A.mid[1 * P + i] = B;
+        A.mid[2 * P + i] = Gxb;
+        A.mid[3 * P + i] = Gyb;
+        A.mid[4 * P + i] = phb;
+    }
+    // fixed-order workgroup reduction of the eps contribution
+    const double w = wave_sum_d(deps);
+    if (tid % 64 == 0) s_red[tid / 64] = w;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int k = 0; k < ANT / 64; ++k) t += s_red[k];
+        A.epart[blockIdx.x] += t;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adj_b(AdjDesc A) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= A.nx || y >= A.ny) return;
+    const int64_t P = A.plane, i = (int64_t)y * A.pitch + x;
+    const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
+    float phb = A.mid[4 * P + i];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
+        const int xs = AX[k] > 0 ? xW : (AX[k] < 0 ? xE : x);
+        const int ys = AY[k] > 0 ? yS : (AY[k] < 0 ? yN : y);
+        const int64_t j = (int64_t)ys * A.pitch + xs;
+        const float w = (k < 5) ? (1.f / 3.f) : (1.f / 12.f);
+        phb += w * (AX[k] * A.mid[2 * P + j] + AY[k] * A.mid[3 * P + j]);
+    }
+    const float Ah = A.mid[0 * P + i];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
+        const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
+        const int xu = AX[q] > 0 ? xW : (AX[q] < 0 ? xE : x);
+        const int yu = AY[q] > 0 ? yS : (AY[q] < 0 ? yN : y);
+        const float ld = A.lin[(5 + q) * P + (int64_t)yd * A.pitch + xd];
+        const float lo = A.lin[(5 + q) * P + i];
+        const float Bu = A.mid[1 * P + (int64_t)yu * A.pitch + xu];
+        A.lout[(5 + q) * P + i] = ld * Ah - Bu * lo + phb;
+    }
+}
+
+// lambda_T: dL/dphi_T on every h_q, zero on g and phi_prev
+__global__ void __launch_bounds__(256) k_adj_seed(AdjDesc A, const float* __restrict__ dphi) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= A.nx || y >= A.ny) return;
+    const int64_t P = A.plane, i = (int64_t)y * A.pitch + x;
+    const float v = dphi[(int64_t)y * A.nx + x];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) A.lout[(5 + q) * P + i] = v;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) A.lout[q * P + i] = 0.f;
+    A.lout[14 * P + i] = 0.f;
+}
+
+// dL/dU_init(x) = sum_q w_q lambda_g,q(x, 0) (the initial g_q = w_q U_init); per-row FP64 sums
+__global__ void __launch_bounds__(256) k_adj_uinit(AdjDesc A, float* __restrict__ dU, double* __restrict__ rows) {
+    __shared__ double s_red[4];
+    const int y = blockIdx.x, tid = threadIdx.x;
+    double acc = 0.0;
+    for (int x = tid; x < A.nx; x += 256) {
+        const int64_t i = (int64_t)y * A.pitch + x;
+        float v = 0.f;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v += AW5[q] * A.lin[q * A.plane + i];
+        dU[(int64_t)y * A.nx + x] = v;
+        acc += v;
+    }
+    const double w = wave_sum_d(acc);
+    if (tid % 64 == 0) s_red[tid / 64] = w;
+    __syncthreads();
+    if (tid == 0) rows[y] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// out[0] = sum of the eps partials, out[1] = sum of the row sums; fixed order
+__global__ void __launch_bounds__(64) k_adj_final(const double* __restrict__ epart, int ne,
+                                                  const double* __restrict__ rows, int nr, double* __restrict__ out) {
+    if (threadIdx.x == 0) {
+        double e = 0.0;
+        for (int k = 0; k < ne; ++k) e += epart[k];
+        out[0] = e;
+    } else if (threadIdx.x == 1) {
+        double u = 0.0;
+        for (int k = 0; k < nr; ++k) u += rows[k];
+        out[1] = u;
+    }
+}
+
+int adj_blocks(const AdjDesc& A) { return ((A.nx + ATX - 1) / ATX) * ((A.ny + ATY - 1) / ATY); }
+
+hipError_t launch_adj_seed(const AdjDesc& A, const float* dphi, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_seed, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A, dphi);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_step(const AdjDesc& A, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_a, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_b, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_finish(const AdjDesc& A, float* dU, double* rows, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_uinit, dim3(A.ny), dim3(256), 0, s, A, dU, rows);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_final, dim3(1), dim3(64), 0, s, A.epart, adj_blocks(A), rows, A.ny, out);
+    return hipGetLastError();
+}
+
+}  // namespace snowlb

@@ -352,6 +352,20 @@ struct snowlb_ctx {
     bool inited = false;
     bool tuned = false;
     std::string err;
+    // discrete adjoint: checkpoints and segment slots [pop planes | phi_prev], adjoint buffers
+    struct {
+        void* slots = nullptr;
+        int64_t slot_bytes = 0, nslots = 0;
+        int n = 0, stride = 0, nck = 0;
+        bool have_forward = false;
+        float* buf = nullptr;  // lambda[0], lambda[1] (15 planes each), intermediates (5 planes)
+        double* epart = nullptr;
+        double* rows = nullptr;
+        double* d_out = nullptr;
+        double* h_out = nullptr;  // pinned, 2 doubles
+        DomDesc* d_segdoms = nullptr;
+        int nsegdoms = 0;
+    } adj;
 };
 
 namespace {
@@ -375,6 +389,13 @@ snowlb_status hip_fail(snowlb_ctx* c, hipError_t e, const char* what) {
 snowlb_status from_driver(snowlb_ctx* c, snowlb_status s) {
     if (s) c->err = c->drv.err;
     return s;
+}
+
+// eps-dependent entries of the descriptor
+void fill_dom_physics_eps(snowlb_ctx* c) {
+    const snowlb_params& p = c->p;
+    c->dom.eps = (float)p.eps;
+    c->dom.aniso_coef = (float)(p.kappa_N * (p.W0 * p.W0 / p.tau0) * p.n_fold * p.eps);
 }
 
 void fill_dom(snowlb_ctx* c) {
@@ -454,7 +475,25 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     return SNOWLB_OK;
 }
 
+void adj_free(snowlb_ctx* c) {
+    if (c->adj.slots) (void)hipFree(c->adj.slots);
+    if (c->adj.buf) (void)hipFree(c->adj.buf);
+    if (c->adj.epart) (void)hipFree(c->adj.epart);
+    if (c->adj.rows) (void)hipFree(c->adj.rows);
+    if (c->adj.d_out) (void)hipFree(c->adj.d_out);
+    if (c->adj.h_out) (void)hipHostFree(c->adj.h_out);
+    if (c->adj.d_segdoms) (void)hipFree(c->adj.d_segdoms);
+    c->adj.slots = nullptr;
+    c->adj.buf = nullptr;
+    c->adj.epart = c->adj.rows = c->adj.d_out = c->adj.h_out = nullptr;
+    c->adj.d_segdoms = nullptr;
+    c->adj.nslots = 0;
+    c->adj.nsegdoms = 0;
+    c->adj.have_forward = false;
+}
+
 void ctx_free(snowlb_ctx* c) {
+    adj_free(c);
     c->drv.release();
     if (c->h_hdr) (void)hipHostFree(c->h_hdr);
     if (c->h_out) (void)hipHostFree(c->h_out);
@@ -773,6 +812,146 @@ snowlb_status snowlb_set_grid_mode(snowlb_ctx* c, int32_t mode) {
 }
 
 int32_t snowlb_get_grid_mode(const snowlb_ctx* c) { return c ? c->drv.grid_mode : -1; }
+
+snowlb_status snowlb_set_eps(snowlb_ctx* c, double eps) {
+    if (!c) return SNOWLB_EINVAL;
+    if (!std::isfinite(eps) || eps < 0 || eps >= 0.5) return fail(c, SNOWLB_EINVAL, "eps must lie in [0, 0.5)");
+    c->p.eps = eps;
+    fill_dom_physics_eps(c);
+    HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
+    return SNOWLB_OK;
+}
+
+// ---------------------------------------------------------------------------------------------- adjoint
+
+static snowlb_status adj_check(snowlb_ctx* c) {
+    if (c->p.flow || c->p.bc_x != SNOWLB_BC_PERIODIC || c->p.storage != SNOWLB_STORE_FP32)
+        return fail(c, SNOWLB_EUNSUPPORTED, "the adjoint supports flow = 0, periodic x and FP32 storage");
+    return SNOWLB_OK;
+}
+
+static char* adj_slot(snowlb_ctx* c, int64_t k) { return (char*)c->adj.slots + k * c->adj.slot_bytes; }
+
+snowlb_status snowlb_adj_forward(snowlb_ctx* c, int32_t n, int32_t stride, void* stream) {
+    if (!c) return SNOWLB_EINVAL;
+    if (snowlb_status st = adj_check(c)) return st;
+    if (n < 1 || stride < 0) return fail(c, SNOWLB_EINVAL, "need n >= 1 and stride >= 0");
+    if (!c->inited) return fail(c, SNOWLB_ESTATE, "adjoint forward before init");
+    hipStream_t s = (hipStream_t)stream;
+    const int st = stride > 0 ? stride : (int)std::ceil(std::sqrt((double)n));
+    const int nck = (n + st - 1) / st;
+    const int64_t slot_bytes = c->pop_bytes + c->phip_bytes;
+    const int64_t need = (int64_t)nck + st;
+    if (c->adj.nslots < need || c->adj.slot_bytes != slot_bytes) {
+        if (c->adj.slots) (void)hipFree(c->adj.slots);
+        c->adj.slots = nullptr;
+        c->adj.nslots = 0;
+        HIPCHK(c, hipMalloc(&c->adj.slots, (size_t)(need * slot_bytes)));
+        c->adj.nslots = need;
+        c->adj.slot_bytes = slot_bytes;
+        c->adj.nsegdoms = 0;  // segment descriptors point into the slots
+    }
+    c->adj.n = n;
+    c->adj.stride = st;
+    c->adj.nck = nck;
+    for (int k = 0; k < nck; ++k) {
+        char* sl = adj_slot(c, k);
+        HIPCHK(c, hipMemcpyAsync(sl, c->dom.pop[c->drv.par], c->pop_bytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(sl + c->pop_bytes, c->dom.phip[c->drv.par], c->phip_bytes, hipMemcpyDeviceToDevice, s));
+        const int len = std::min(st, n - k * st);
+        snowlb_status r = from_driver(c, c->drv.run(len, s));
+        if (r) return r;
+    }
+    c->adj.have_forward = true;
+    return SNOWLB_OK;
+}
+
+snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, double* deps, double* dU0,
+                                  void* stream) {
+    if (!c) return SNOWLB_EINVAL;
+    if (snowlb_status st = adj_check(c)) return st;
+    if (!dphi || !dU || !deps || !dU0) return fail(c, SNOWLB_EINVAL, "NULL argument");
+    if (!c->adj.have_forward) return fail(c, SNOWLB_ESTATE, "adjoint backward before adjoint forward");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t P = c->dom.plane, pb = P * 4;
+    AdjDesc A{};
+    A.nx = c->p.nx;
+    A.ny = c->p.ny;
+    A.pitch = c->dom.pitch;
+    A.n_fold = c->p.n_fold;
+    A.plane = P;
+    A.grad_eps2 = c->p.grad_eps2;
+    A.eps = c->dom.eps;
+    A.Dphi = c->dom.Dphi;
+    A.coefN = (float)(c->p.kappa_N * (c->p.W0 * c->p.W0 / c->p.tau0) * c->p.n_fold);
+    A.inv_tau0 = c->dom.inv_tau0;
+    A.lam = c->dom.lam;
+    A.half_Lsat = c->dom.half_Lsat;
+    A.tauv_m_half = c->dom.tauv_m_half;
+    const int nblk = adj_blocks(A);
+    if (!c->adj.buf) {
+        HIPCHK(c, hipMalloc(&c->adj.buf, (size_t)(35 * pb)));
+        HIPCHK(c, hipMalloc(&c->adj.epart, (size_t)nblk * sizeof(double)));
+        HIPCHK(c, hipMalloc(&c->adj.rows, (size_t)c->p.ny * sizeof(double)));
+        HIPCHK(c, hipMalloc(&c->adj.d_out, 2 * sizeof(double)));
+        HIPCHK(c, hipHostMalloc(&c->adj.h_out, 2 * sizeof(double), hipHostMallocDefault));
+    }
+    const int st = c->adj.stride, n = c->adj.n;
+    if (c->adj.nsegdoms != std::max(st - 1, 1)) {
+        std::vector<DomDesc> h((size_t)std::max(st - 1, 1), c->dom);
+        for (int i = 0; i + 1 < st; ++i) {
+            char* a = adj_slot(c, c->adj.nck + i);
+            char* b = adj_slot(c, c->adj.nck + i + 1);
+            h[i].pop[0] = a;
+            h[i].pop[1] = b;
+            h[i].phip[0] = (float*)(a + c->pop_bytes);
+            h[i].phip[1] = (float*)(b + c->pop_bytes);
+        }
+        if (c->adj.d_segdoms) (void)hipFree(c->adj.d_segdoms);
+        c->adj.d_segdoms = nullptr;
+        HIPCHK(c, hipMalloc(&c->adj.d_segdoms, h.size() * sizeof(DomDesc)));
+        HIPCHK(c, hipMemcpy(c->adj.d_segdoms, h.data(), h.size() * sizeof(DomDesc), hipMemcpyHostToDevice));
+        c->adj.nsegdoms = (int)h.size();
+    }
+    float* lam[2] = {c->adj.buf, c->adj.buf + 15 * P};
+    A.mid = c->adj.buf + 30 * P;
+    A.epart = c->adj.epart;
+    HIPCHK(c, hipMemsetAsync(c->adj.epart, 0, (size_t)nblk * sizeof(double), s));
+    A.lout = lam[0];
+    hipError_t e = launch_adj_seed(A, dphi, s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint seed kernel");
+    Driver& D = c->drv;
+    snowlb_status r = from_driver(c, D.ensure_tiles(D.tile));
+    if (r) return r;
+    const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, D.grid_mode);
+    int cur = 0;
+    for (int k = c->adj.nck - 1; k >= 0; --k) {
+        const int len = std::min(st, n - k * st);
+        HIPCHK(c, hipMemcpyAsync(adj_slot(c, c->adj.nck), adj_slot(c, k), (size_t)c->adj.slot_bytes,
+                                 hipMemcpyDeviceToDevice, s));
+        for (int i = 0; i + 1 < len; ++i) {
+            e = launch_step(D.tile, c->p.storage, 0, 0, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile],
+                            grid, 0, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint recompute step");
+        }
+        for (int i = len - 1; i >= 0; --i) {
+            A.st = (const float*)adj_slot(c, c->adj.nck + i);
+            A.lin = lam[cur];
+            A.lout = lam[1 - cur];
+            e = launch_adj_step(A, s);
+            if (e != hipSuccess) return hip_fail(c, e, "adjoint step kernels");
+            cur ^= 1;
+        }
+    }
+    A.lin = lam[cur];
+    e = launch_adj_finish(A, dU, c->adj.rows, c->adj.d_out, s);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint reduction kernels");
+    HIPCHK(c, hipMemcpyAsync(c->adj.h_out, c->adj.d_out, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *deps = c->adj.h_out[0];
+    *dU0 = c->adj.h_out[1];
+    return SNOWLB_OK;
+}
 
 // ---------------------------------------------------------------------------------------------- batch
 

@@ -73,4 +73,22 @@ hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out,
 
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 
+// ---- discrete adjoint (snowlb_adjoint.hip): no flow, periodic, FP32 storage
+struct AdjDesc {
+    int32_t nx, ny, pitch, n_fold;
+    int64_t plane;       // elements between planes of every slot below
+    const float* st;     // state at t: g_0..4, h_0..8
+    const float* lin;    // lambda(t+1): g_0..4, h_0..8, phi_prev
+    float* lout;         // lambda(t)
+    float* mid;          // A_h, B, Gbar_x, Gbar_y, phibar
+    double* epart;       // per-workgroup dL/deps partials, accumulated over the reverse sweep
+    double grad_eps2;
+    float eps, Dphi, coefN, inv_tau0, lam, half_Lsat, tauv_m_half, pad_;
+};
+int adj_blocks(const AdjDesc& A);
+hipError_t launch_adj_seed(const AdjDesc& A, const float* dphi, hipStream_t s);
+hipError_t launch_adj_step(const AdjDesc& A, hipStream_t s);
+// dU[y*nx + x] = dL/dU_init; rows: ny doubles of scratch; out[0] = dL/deps, out[1] = sum dU
+hipError_t launch_adj_finish(const AdjDesc& A, float* dU, double* rows, double* out, hipStream_t s);
+
 }  // namespace snowlb

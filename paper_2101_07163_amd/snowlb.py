@@ -73,6 +73,9 @@ _SIGS = {
     "snowlb_set_grid_mode": (ctypes.c_int32, [_v, ctypes.c_int32]),
     "snowlb_get_grid_mode": (ctypes.c_int32, [_v]),
     "snowlb_bw_probe": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
+    "snowlb_set_eps": (ctypes.c_int32, [_v, ctypes.c_double]),
+    "snowlb_adj_forward": (ctypes.c_int32, [_v, ctypes.c_int32, ctypes.c_int32, _v]),
+    "snowlb_adj_backward": (ctypes.c_int32, [_v, _v, _v, _P(ctypes.c_double), _P(ctypes.c_double), _v]),
     "snowlb_batch_create": (ctypes.c_int32, [_P(snowlb_params), ctypes.c_int32, _P(_v)]),
     "snowlb_batch_destroy": (None, [_v]),
     "snowlb_batch_size": (ctypes.c_int32, [_v]),
@@ -214,6 +217,21 @@ def snowlb_get_grid_mode(ctx) -> int:
 
 def snowlb_bw_probe(dst_dev: int, src_dev: int, nbytes: int, stream: int) -> None:
     _check(lib().snowlb_bw_probe(dst_dev, src_dev, nbytes, stream), None)
+
+
+def snowlb_set_eps(ctx, eps: float) -> None:
+    _check(lib().snowlb_set_eps(ctx, float(eps)), ctx)
+
+
+def snowlb_adj_forward(ctx, n_steps: int, ckpt_stride: int, stream: int) -> None:
+    _check(lib().snowlb_adj_forward(ctx, int(n_steps), int(ckpt_stride), stream), ctx)
+
+
+def snowlb_adj_backward(ctx, dL_dphiT_dev: int, dL_dUinit_dev: int, stream: int) -> tuple[float, float]:
+    de, du = ctypes.c_double(), ctypes.c_double()
+    _check(lib().snowlb_adj_backward(ctx, dL_dphiT_dev, dL_dUinit_dev, ctypes.byref(de), ctypes.byref(du),
+                                     stream), ctx)
+    return de.value, du.value
 
 
 def snowlb_batch_create(params: list) -> ctypes.c_void_p:
@@ -456,3 +474,47 @@ class Batch:
     @property
     def tile(self) -> int:
         return snowlb_batch_get_tile(self.b)
+
+
+def _adjoint_function():
+    import torch
+
+    class SnowAdjoint(torch.autograd.Function):
+        """phi_T = SnowAdjoint.apply(eps, U_init, sim, n_steps, ckpt_stride).
+
+        Forward: set eps, initialise the context `sim` (no flow, periodic, FP32) with the initial
+        supersaturation field U_init, run n_steps with checkpoints every ckpt_stride steps (0: sqrt).
+        Backward: the library's hand-written adjoint gives dL/deps and dL/dU_init from dL/dphi_T;
+        gradients with respect to anything U_init was built from (e.g. U0) follow by autograd.
+        """
+
+        @staticmethod
+        def forward(ctx, eps, U_init, sim, n_steps, ckpt_stride=0):
+            snowlb_set_eps(sim.ctx, float(eps))
+            sim.init(U_init.detach())
+            snowlb_adj_forward(sim.ctx, int(n_steps), int(ckpt_stride), sim.stream)
+            ctx.sim = sim
+            ctx.eps_like = eps
+            return sim.read("phi")
+
+        @staticmethod
+        def backward(ctx, grad_phi):
+            sim = ctx.sim
+            g = grad_phi.detach().to(torch.float32).contiguous()
+            dU = torch.empty_like(g)
+            de, _ = snowlb_adj_backward(sim.ctx, g.data_ptr(), dU.data_ptr(), sim.stream)
+            d_eps = torch.as_tensor(de, dtype=ctx.eps_like.dtype, device=ctx.eps_like.device)
+            return d_eps, dU, None, None, None
+
+    return SnowAdjoint
+
+
+_SNOW_ADJOINT = None
+
+
+def snow_adjoint(eps, U_init, sim: Sim, n_steps: int, ckpt_stride: int = 0):
+    """Differentiable phi_T(eps, U_init) through the library's discrete adjoint (see SnowAdjoint)."""
+    global _SNOW_ADJOINT
+    if _SNOW_ADJOINT is None:
+        _SNOW_ADJOINT = _adjoint_function()
+    return _SNOW_ADJOINT.apply(eps, U_init, sim, n_steps, ckpt_stride)
