@@ -63,7 +63,8 @@ typedef int32_t snowlb_status;
 #define SNOWLB_POP_PHIP 3 /* 1 plane: phi at the previous step          */
 
 typedef struct {
-    int32_t nx, ny;     /* lattice size, >= 2 each                                             */
+    int32_t nx, ny;     /* lattice size: 2 <= nx, ny <= 65536, and at most 2^30 cells once padded
+                           to whole 64 x 4 blocks (every in-plane byte offset fits 32 bits)   */
     int32_t flow;       /* 1: D2Q9 flow solver on; 0: u = 0 (no f populations stored)           */
     int32_t bc_x;       /* SNOWLB_BC_PERIODIC or SNOWLB_BC_INOUT (needs flow = 1)               */
     int32_t storage;    /* SNOWLB_STORE_*                                                       */

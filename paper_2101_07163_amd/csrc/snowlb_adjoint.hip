@@ -13,9 +13,9 @@
 //   k_adj_b (per cell x): lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x)   [through h*_q(x)]
 //                                           - B(x - c_q) lambda_h,q(x)      [destination term of Eq. (d)]
 //                                           + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)   [phi = sum h]
-// Layout: every field is a pitched FP32 plane with the state's plane stride; the state slot holds g_0..4
-// then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev; the intermediate slot holds A_h, B,
-// Gbar_x, Gbar_y, phibar.
+// Layout: every field is an FP32 plane in the cell order of the state, with the state's plane stride;
+// the state slot holds g_0..4 then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev; the
+// intermediate slot holds A_h, B, Gbar_x, Gbar_y, phibar.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
     for (int r = tid; r < ALN; r += ANT) {
         const int lx = r % ALX, ly = r / ALX;
         const int gx = ((x0 + lx - 1) % A.nx + A.nx) % A.nx, gy = ((y0 + ly - 1) % A.ny + A.ny) % A.ny;
-        const int64_t i = (int64_t)gy * A.pitch + gx;
+        const int64_t i = cell_index(A.nbx, gx, gy);
         double p = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) p += (double)hpl[q * P + i];
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
     double deps = 0.0;
     if (active) {
         const int own = (ty + 1) * ALX + tx + 1;
-        const int64_t i = (int64_t)y * A.pitch + x;
+        const int64_t i = cell_index(A.nbx, x, y);
         float h[9], g[5];
 #pragma unroll
         for (int q = 0; q < 9; ++q) h[q] = hpl[q * P + i];
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
         for (int q = 0; q < 9; ++q) {
             const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
             const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
-            const int64_t di = (int64_t)yd * A.pitch + xd;
+            const int64_t di = cell_index(A.nbx, xd, yd);
             const float Pb = A.lin[(5 + q) * P + di];  // lambda_h,q(x + c_q, t + 1)
             const float hold = hpl[q * P + di];         // h_q(x + c_q, t)
             const float heq = AW9[q] * (phi - 3.f * (AX[q] * Nx + AY[q] * Ny));
@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
         for (int q = 0; q < 5; ++q) {
             const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
             const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
-            gsb[q] = A.lin[q * P + (int64_t)yd * A.pitch + xd];
+            gsb[q] = A.lin[q * P + cell_index(A.nbx, xd, yd)];
             itgb -= gsb[q] * (g[q] - AW5[q] * U);
             Ub += AW5[q] * gsb[q] * itg;
             srcb -= AW5[q] * gsb[q];
@@ -188,14 +188,14 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
 __global__ void __launch_bounds__(256) k_adj_b(AdjDesc A) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= A.nx || y >= A.ny) return;
-    const int64_t P = A.plane, i = (int64_t)y * A.pitch + x;
+    const int64_t P = A.plane, i = cell_index(A.nbx, x, y);
     const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
     float phb = A.mid[4 * P + i];
 #pragma unroll
     for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
         const int xs = AX[k] > 0 ? xW : (AX[k] < 0 ? xE : x);
         const int ys = AY[k] > 0 ? yS : (AY[k] < 0 ? yN : y);
-        const int64_t j = (int64_t)ys * A.pitch + xs;
+        const int64_t j = cell_index(A.nbx, xs, ys);
         const float w = (k < 5) ? (1.f / 3.f) : (1.f / 12.f);
         phb += w * (AX[k] * A.mid[2 * P + j] + AY[k] * A.mid[3 * P + j]);
     }
@@ -206,9 +206,9 @@ __global__ void __launch_bounds__(256) k_adj_b(AdjDesc A) {
         const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
         const int xu = AX[q] > 0 ? xW : (AX[q] < 0 ? xE : x);
         const int yu = AY[q] > 0 ? yS : (AY[q] < 0 ? yN : y);
-        const float ld = A.lin[(5 + q) * P + (int64_t)yd * A.pitch + xd];
+        const float ld = A.lin[(5 + q) * P + cell_index(A.nbx, xd, yd)];
         const float lo = A.lin[(5 + q) * P + i];
-        const float Bu = A.mid[1 * P + (int64_t)yu * A.pitch + xu];
+        const float Bu = A.mid[1 * P + cell_index(A.nbx, xu, yu)];
         A.lout[(5 + q) * P + i] = ld * Ah - Bu * lo + phb;
     }
 }
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(256) k_adj_b(AdjDesc A) {
 __global__ void __launch_bounds__(256) k_adj_seed(AdjDesc A, const float* __restrict__ dphi) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= A.nx || y >= A.ny) return;
-    const int64_t P = A.plane, i = (int64_t)y * A.pitch + x;
+    const int64_t P = A.plane, i = cell_index(A.nbx, x, y);
     const float v = dphi[(int64_t)y * A.nx + x];
 #pragma unroll
     for (int q = 0; q < 9; ++q) A.lout[(5 + q) * P + i] = v;
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_adj_uinit(AdjDesc A, float* __restrict_
     const int y = blockIdx.x, tid = threadIdx.x;
     double acc = 0.0;
     for (int x = tid; x < A.nx; x += 256) {
-        const int64_t i = (int64_t)y * A.pitch + x;
+        const int64_t i = cell_index(A.nbx, x, y);
         float v = 0.f;
 #pragma unroll
         for (int q = 0; q < 5; ++q) v += AW5[q] * A.lin[q * A.plane + i];

@@ -45,7 +45,7 @@ struct StateHeader {
     int64_t pop_bytes, phip_bytes, refs_bytes;
     uint64_t pad[9];
 };
-constexpr uint64_t kMagic = 0x534e4f574c423032ull;  // "SNOWLB02"
+constexpr uint64_t kMagic = 0x534e4f574c423033ull;  // "SNOWLB03": 64 x 4 blocked cell order
 static_assert(sizeof(StateHeader) == 128, "header size");
 constexpr int64_t kHeaderBytes = 256;
 
@@ -309,8 +309,9 @@ bool finite_all(const snowlb_params* p) {
 const char* validate_msg(const snowlb_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 2 || p->ny < 2) return "nx and ny must be >= 2";
-    if (p->nx > 65536 || p->ny > 65536 || (int64_t)p->nx * p->ny > (int64_t)1 << 31)
-        return "lattice too large (nx, ny <= 65536, nx*ny <= 2^31)";
+    if (p->nx > 65536 || p->ny > 65536 ||
+        round_up(p->nx, kBlockX) * round_up(p->ny, kBlockY) > kMaxPlaneCells)
+        return "lattice too large (nx, ny <= 65536 and, padded to 64 x 4 blocks, at most 2^30 cells)";
     if (p->flow != 0 && p->flow != 1) return "flow must be 0 or 1";
     if (p->bc_x != SNOWLB_BC_PERIODIC && p->bc_x != SNOWLB_BC_INOUT) return "unknown bc_x";
     if (p->bc_x == SNOWLB_BC_INOUT && !p->flow) return "inflow/outflow needs flow = 1";
@@ -438,19 +439,20 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     const snowlb_params* p = &c->p;
     c->esize = p->storage == SNOWLB_STORE_FP32 ? 4 : 2;
     fill_dom(c);
-    // geometry: rows 256-byte aligned; planes padded to 64 KiB then staggered by 9 x 256 B
+    // geometry: cells in blocks of 64 x 4 (the lattice padded up to whole blocks); planes padded to
+    // 64 KiB then staggered by 9 x 256 B
     const int64_t stagger = env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
-    const int64_t row_align = 256 / c->esize;
-    const int64_t pitch = round_up(p->nx, row_align);
-    const int64_t plane_bytes = round_up(pitch * p->ny * c->esize, 65536) + stagger;
-    c->dom.pitch = (int32_t)pitch;
+    const int64_t nbx = (p->nx + kBlockX - 1) / kBlockX;
+    const int64_t cells = nbx * kBlockX * round_up(p->ny, kBlockY);
+    const int64_t plane_bytes = round_up(cells * c->esize, 65536) + stagger;
+    c->dom.nbx = (int32_t)nbx;
     c->dom.plane = plane_bytes / c->esize;
     c->pop_bytes = round_up(plane_bytes * c->dom.npop, 65536);
-    c->phip_bytes = round_up(pitch * p->ny * 4, 65536) + stagger;
+    c->phip_bytes = round_up(cells * 4, 65536) + stagger;
     c->local_ref = p->storage != SNOWLB_STORE_FP32;
     int64_t rplane_bytes = 0;
     if (c->local_ref) {
-        rplane_bytes = round_up(pitch * p->ny * c->esize, 65536) + stagger;
+        rplane_bytes = round_up(cells * c->esize, 65536) + stagger;
         c->refs_bytes = round_up(rplane_bytes * (p->flow ? 4 : 1), 65536);
     }
     const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
@@ -877,7 +879,7 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     AdjDesc A{};
     A.nx = c->p.nx;
     A.ny = c->p.ny;
-    A.pitch = c->dom.pitch;
+    A.nbx = c->dom.nbx;
     A.n_fold = c->p.n_fold;
     A.plane = P;
     A.grad_eps2 = c->p.grad_eps2;

@@ -1,9 +1,9 @@
 // snowlb_internal.h -- descriptors shared by the HIP kernels and the host runtime of libsnowlb.
 //
-// Device layout (per domain): structure-of-arrays population planes, each ny rows of `pitch`
-// elements (x fastest, pitch a multiple of 64 elements so every row starts 256-byte aligned),
-// consecutive planes `plane` elements apart (padded and staggered so that the 23 streams of one
-// tile do not start on the same HBM channel).  Plane order: f_0..f_8 (flow only), g_0..g_4,
+// Device layout (per domain): structure-of-arrays population planes.  Inside a plane the cells are
+// ordered in blocks of 64 x 4 (cell_index below): blocks along x, block rows along y, each block
+// 4 rows of 64 cells.  Consecutive planes are `plane` elements apart (padded and staggered so that
+// the 23 streams of one tile do not start on the same HBM channel).  Plane order: f_0..f_8 (flow only), g_0..g_4,
 // h_0..h_8.  Two copies (pop[0], pop[1]) ping-pong between steps, and so do the FP32 plane phi_prev
 // and (16-bit storage only) the 16-bit reference planes U, rho, jx, jy that neighbours read to
 // decode the populations a cell emitted.
@@ -13,11 +13,31 @@
 
 namespace snowlb {
 
+// address space of device global memory (lets the compiler emit global rather than flat accesses)
+#define GMEM __attribute__((address_space(1)))
+
+// Position of cell (x, y) inside a plane whose rows hold nbx blocks of 64 x 4 cells.  A workgroup
+// tile of 64 x 4 cells is then one contiguous 256-element run per plane, so the workgroups resident
+// at one time sweep a dense address range.  The index is separable into an x part and a y part.
+// Valid for 0 <= x < 64 nbx and 0 <= y with 64 nbx * round_up(y + 1, 4) <= 2^30 (the plane limit).
+constexpr int kBlockX = 64, kBlockY = 4;
+constexpr int64_t kMaxPlaneCells = int64_t(1) << 30;  // keeps every in-plane byte offset below 2^32
+__host__ __device__ __forceinline__ uint32_t cell_xpart(int x) {
+    return ((uint32_t)(x >> 6) << 8) + (uint32_t)(x & 63);
+}
+__host__ __device__ __forceinline__ uint32_t cell_ypart(int nbx, int y) {
+    return (uint32_t)(y >> 2) * ((uint32_t)nbx << 8) + ((uint32_t)(y & 3) << 6);
+}
+__host__ __device__ __forceinline__ int64_t cell_index(int nbx, int x, int y) {
+    return (int64_t)cell_ypart(nbx, y) + cell_xpart(x);
+}
+
 struct DomDesc {
-    int32_t nx, ny, pitch, npop;  // npop: planes per copy (23 with flow, 14 without)
+    int32_t nx, ny, nbx, npop;    // nbx: 64 x 4 blocks per block row; npop: planes per copy (23 with
+                                  // flow, 14 without)
     int64_t plane;                // elements between consecutive planes
     void* pop[2];                 // the two population copies
-    float* phip[2];               // phi(t-1), FP32, pitched
+    float* phip[2];               // phi(t-1), FP32, same cell order
     void* refs[2];                // 16-bit storage only: reference planes U, rho, jx, jy (else null)
     int64_t rplane;               // elements between consecutive reference planes
     double grad_eps2;             // |grad phi|^2 (FP64) at or below which a = 1 and N = 0
@@ -75,7 +95,7 @@ hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s)
 
 // ---- discrete adjoint (snowlb_adjoint.hip): no flow, periodic, FP32 storage
 struct AdjDesc {
-    int32_t nx, ny, pitch, n_fold;
+    int32_t nx, ny, nbx, n_fold;
     int64_t plane;       // elements between planes of every slot below
     const float* st;     // state at t: g_0..4, h_0..8
     const float* lin;    // lambda(t+1): g_0..4, h_0..8, phi_prev

@@ -104,48 +104,54 @@ __device__ __forceinline__ int wrapi(int i, int n) {
     return i;
 }
 
+// Every buffer lives in device global memory.  The plane pointers are read from the descriptor,
+// so the compiler cannot infer that and would emit flat (generic) accesses, which wait on both the
+// memory and the LDS counters; the casts below make them global accesses.
 template <class S>
-__device__ __forceinline__ const typename S::T* plane_ptr(const DomDesc& d, int par, int q) {
-    return reinterpret_cast<const typename S::T*>(d.pop[par]) + (int64_t)q * d.plane;
+__device__ __forceinline__ const GMEM typename S::T* plane_ptr(const DomDesc& d, int par, int q) {
+    return (const GMEM typename S::T*)(d.pop[par]) + (int64_t)q * d.plane;
 }
 template <class S>
-__device__ __forceinline__ typename S::T* plane_ptr_w(const DomDesc& d, int par, int q) {
-    return reinterpret_cast<typename S::T*>(d.pop[par]) + (int64_t)q * d.plane;
+__device__ __forceinline__ GMEM typename S::T* plane_ptr_w(const DomDesc& d, int par, int q) {
+    return (GMEM typename S::T*)(d.pop[par]) + (int64_t)q * d.plane;
+}
+__device__ __forceinline__ GMEM float* phip_ptr(const DomDesc& d, int par) {
+    return (GMEM float*)(d.phip[par]);
 }
 
 // Closure of the domain for a lattice position (gx, gy) that may lie outside it: y periodic; x
 // periodic, or (inlet/outlet) the inlet ghost left of x = 0 (returns false) and a copy of column
-// nx-1 right of it.
+// nx-1 right of it.  eo receives the in-plane element offset of the position it maps to.
 template <bool INOUT>
-__device__ __forceinline__ bool map_pos(const DomDesc& d, int gx, int gy, int64_t& idx) {
+__device__ __forceinline__ bool map_off(const DomDesc& d, int gx, int gy, uint32_t& eo) {
     const int sy = wrapi(gy, d.ny);
     int sx;
     if (INOUT) {
         if (gx < 0) {
-            idx = 0;
+            eo = 0;
             return false;
         }
         sx = gx < d.nx ? gx : d.nx - 1;
     } else {
         sx = wrapi(gx, d.nx);
     }
-    idx = (int64_t)sy * d.pitch + sx;
+    eo = cell_xpart(sx) + cell_ypart(d.nbx, sy);
     return true;
 }
 
-// The 9 h populations of the cell at idx and phi = sum h, summed in FP64: phi is close to -1 or 1 in
-// the bulk, and an E4 gradient of FP32 sums would carry cancellation error of order 1e-7 / |grad phi|
-// into the direction of the normal, i.e. into a_s and N where |grad phi| is small.
-template <class S>
-__device__ __forceinline__ double load_h(const DomDesc& d, int par, int64_t idx, float h[9]) {
-    const float ref = S::kLocalRef ? d.phip[par][idx] : 0.f;
-    double phi = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        h[q] = S::dec(plane_ptr<S>(d, par, d.off_h + q)[idx], W9[q], ref);
-        phi += (double)h[q];
-    }
-    return phi;
+// Global accesses of the step: a base that is uniform over the workgroup plus a 32-bit per-lane
+// byte offset.  The empty asm pins the base in scalar registers and keeps the compiler from folding
+// the plane stride into a 64-bit per-lane address, so each access is one global load or store in
+// scalar-base + vector-offset form (every caller passes a workgroup-uniform base).
+template <class T>
+__device__ __forceinline__ T gld(const GMEM char* base, uint32_t boff) {
+    asm("" : "+s"(base));
+    return *(const GMEM T*)(base + boff);
+}
+template <class T>
+__device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
+    asm("" : "+s"(base));
+    *(GMEM T*)(base + boff) = v;
 }
 
 // Reference values (U, rho, jx, jy) of lattice position (gx, gy) with the closure: the inlet ghost
@@ -169,8 +175,8 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
     } else {
         gx = wrapi(gx, d.nx);
     }
-    const int64_t i = (int64_t)sy * d.pitch + gx;
-    const typename S::T* b = reinterpret_cast<const typename S::T*>(d.refs[par]);
+    const int64_t i = cell_index(d.nbx, gx, sy);
+    const GMEM typename S::T* b = (const GMEM typename S::T*)(d.refs[par]);
     r[R_U] = S::from_ref(b[i]);
     if (d.npop == 23) {
         r[R_RHO] = S::from_ref(b[d.rplane + i]);
@@ -185,8 +191,8 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
 template <class S>
 __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, int y, bool flow, float f[9],
                                             float g[5], float h[9]) {
-    const int64_t i = (int64_t)y * d.pitch + x;
-    const float hr = S::kLocalRef ? d.phip[par][i] : 0.f;
+    const int64_t i = cell_index(d.nbx, x, y);
+    const float hr = S::kLocalRef ? phip_ptr(d, par)[i] : 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) h[q] = S::dec(plane_ptr<S>(d, par, d.off_h + q)[i], W9[q], hr);
 #pragma unroll
@@ -204,11 +210,14 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
 template <int TX, int TY, class S, bool FLOW, bool INOUT>
 __global__ void __launch_bounds__(TX * TY)
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
+    using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
     constexpr int NR = REF ? (FLOW ? 4 : 1) : 1;  // reference planes staged in LDS
     constexpr int NT = TX * TY;
     constexpr int LX = TX + 2, LY = TY + 2, LN = LX * LY;
     constexpr int RING = 2 * LX + 2 * TY;
+    constexpr int PF = 0, PG = FLOW ? 9 : 0, PH = PG + 5;  // first plane of f, g and h in a copy
+    constexpr uint32_t ES = sizeof(T);
     __shared__ double s_phi[LN];
     __shared__ float s_h[9][LN];
     __shared__ float s_ref[NR][REF ? LN : 1];
@@ -216,6 +225,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int own = (ty + 1) * LX + (tx + 1);
+    const int npar = 1 - par;
 
     // XCD-aware order (optional): consecutive workgroup ids are spread over the 8 XCDs; give each
     // XCD a contiguous run of tiles so neighbouring tiles share halo lines in that XCD's L2.
@@ -224,33 +234,87 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     const int per_xcd = G / 8;
     const int slot = (xcd_remap && G % 8 == 0) ? ((b % 8) * per_xcd + b / 8) : b;
 
+    auto ring_pos = [&](int r, int& lx, int& ly) {
+        if (r < LX) { lx = r; ly = 0; }
+        else if (r < 2 * LX) { lx = r - LX; ly = LY - 1; }
+        else if (r < 2 * LX + TY) { lx = 0; ly = 1 + (r - 2 * LX); }
+        else { lx = LX - 1; ly = 1 + (r - 2 * LX - TY); }
+    };
+
     for (int t = slot; t < ntiles; t += G) {
         const TileDesc td = tiles[t];
         const DomDesc& d = doms[td.dom];
+        // uniform bases: population copies, phi_prev, reference planes
+        const uint64_t pb = (uint64_t)d.plane * ES;   // bytes between population planes
+        const uint64_t rb = (uint64_t)d.rplane * ES;  // bytes between reference planes
+        const GMEM char* pin = (const GMEM char*)d.pop[par];
+        GMEM char* pout = (GMEM char*)d.pop[npar];
+        const GMEM char* phin = (const GMEM char*)d.phip[par];
+        GMEM char* phout = (GMEM char*)d.phip[npar];
+        const GMEM char* rin = REF ? (const GMEM char*)d.refs[par] : nullptr;
+        GMEM char* rout = REF ? (GMEM char*)d.refs[npar] : nullptr;
+
         const int x = td.x0 + tx, y = td.y0 + ty;
         const bool active = (x < d.nx) && (y < d.ny);
-        const int64_t cidx = (int64_t)y * d.pitch + x;
-        const typename S::T* rbase = REF ? reinterpret_cast<const typename S::T*>(d.refs[par]) : nullptr;
+        const uint32_t xp = cell_xpart(x), yp = cell_ypart(d.nbx, y);
+        const uint32_t co = xp + yp;  // element offset of this lane's cell (active lanes)
 
-        // ---- own cell first (all threads; ragged positions hold wrapped / ghost data): raw loads
-        typename S::T graw[5], fraw[9];
-        float phip = 0.f;
+        // ---- issue every global load of this tile first (own position and the first pass over the
+        // halo ring, with the 16-bit references that decode them), so that they are all in flight
+        // together; decode and stage afterwards.  Lanes outside the domain stage the position their
+        // LDS slot stands for, which can be the halo of an active neighbour.
+        T graw[5], fraw[9], hraw[9], rraw[9];
+        T oref[NR], rref[NR];
+        float ophi = 0.f, rphi = 0.f;  // phi_prev of the staged positions
+        uint32_t oo;
+        const bool oreal = map_off<INOUT>(d, x, y, oo);  // oo == co for active lanes
+        if (oreal) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) hraw[q] = gld<T>(pin + (PH + q) * pb, oo * ES);
+            ophi = gld<float>(phin, oo * 4);
+            if (REF) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) oref[k] = gld<T>(rin + k * rb, oo * ES);
+            }
+        }
         if (active) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) graw[q] = plane_ptr<S>(d, par, d.off_g + q)[cidx];
+            for (int q = 0; q < 5; ++q) graw[q] = gld<T>(pin + (PG + q) * pb, co * ES);
             if (FLOW) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) fraw[q] = plane_ptr<S>(d, par, q)[cidx];
+                for (int q = 0; q < 9; ++q) fraw[q] = gld<T>(pin + (PF + q) * pb, co * ES);
             }
-            phip = d.phip[par][cidx];
         }
-        // stage phi, h and (16-bit storage) the reference values of one lattice position
-        auto stage = [&](int gx, int gy, int li, float hh[9]) {
-            int64_t idx;
-            const bool real = map_pos<INOUT>(d, gx, gy, idx);
+        int rlx = 0, rly = 0;
+        uint32_t ro = 0;
+        bool rreal = false;
+        const bool has_ring = tid < RING;
+        if (has_ring) {
+            ring_pos(tid, rlx, rly);
+            rreal = map_off<INOUT>(d, td.x0 + rlx - 1, td.y0 + rly - 1, ro);
+            if (rreal) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) rraw[q] = gld<T>(pin + (PH + q) * pb, ro * ES);
+                if (REF) {
+                    rphi = gld<float>(phin, ro * 4);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) rref[k] = gld<T>(rin + k * rb, ro * ES);
+                }
+            }
+        }
+        // Decode h of one staged position and write phi, h and the 16-bit references to LDS.  phi is
+        // summed in FP64: it is close to -1 or 1 in the bulk, and an E4 gradient of FP32 sums would
+        // carry cancellation error of order 1e-7 / |grad phi| into the direction of the normal, i.e.
+        // into a and N where |grad phi| is small.  h is stored against its holder's phi_prev.
+        auto stage = [&](bool real, const T raw[9], float href, const T refs[NR], int li, float hh[9]) {
             double p64 = -1.0;  // inlet ghost: phi = -1 (its h are never read)
             if (real) {
-                p64 = load_h<S>(d, par, idx, hh);
+                p64 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    hh[q] = S::dec(raw[q], W9[q], href);
+                    p64 += (double)hh[q];
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) hh[q] = 0.f;
@@ -261,7 +325,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             if (REF) {
                 if (real) {
 #pragma unroll
-                    for (int k = 0; k < NR; ++k) s_ref[k][li] = S::from_ref(rbase[k * d.rplane + idx]);
+                    for (int k = 0; k < NR; ++k) s_ref[k][li] = S::from_ref(refs[k]);
                 } else {
                     s_ref[R_U][li] = S::from_ref(S::to_ref(d.U_in));
                     if (FLOW) {
@@ -273,21 +337,35 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             }
         };
         float h[9];
-        stage(x, y, own, h);
-
-        // ---- halo ring
-        for (int r = tid; r < RING; r += NT) {
-            int lx, ly;
-            if (r < LX) { lx = r; ly = 0; }
-            else if (r < 2 * LX) { lx = r - LX; ly = LY - 1; }
-            else if (r < 2 * LX + TY) { lx = 0; ly = 1 + (r - 2 * LX); }
-            else { lx = LX - 1; ly = 1 + (r - 2 * LX - TY); }
+        stage(oreal, hraw, ophi, oref, own, h);
+        if (has_ring) {
             float hr[9];
-            stage(td.x0 + lx - 1, td.y0 + ly - 1, ly * LX + lx, hr);
+            stage(rreal, rraw, rphi, rref, rly * LX + rlx, hr);
+        }
+        // rings larger than the workgroup (e.g. 128 x 2 tiles) take further passes
+        for (int r = tid + NT; r < RING; r += NT) {
+            int lx, ly;
+            ring_pos(r, lx, ly);
+            uint32_t eo;
+            const bool real = map_off<INOUT>(d, td.x0 + lx - 1, td.y0 + ly - 1, eo);
+            T raw[9], refs[NR];
+            float pr = 0.f;
+            if (real) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) raw[q] = gld<T>(pin + (PH + q) * pb, eo * ES);
+                if (REF) {
+                    pr = gld<float>(phin, eo * 4);
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) refs[k] = gld<T>(rin + k * rb, eo * ES);
+                }
+            }
+            float hr[9];
+            stage(real, raw, pr, refs, ly * LX + lx, hr);
         }
         __syncthreads();
 
         if (active) {
+            const float phip = ophi;  // phi(t-1) of this cell
             // ---- vapour and flow populations (16-bit: references of their source cells)
             float g[5], f[9];
 #pragma unroll
@@ -320,9 +398,10 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             // polynomials in the unit normal (theta-free, sign-free): with X = gx^2/|g|^2,
             // Y = gy^2/|g|^2, cos 6t = X^3 - 15 X^2 Y + 15 X Y^2 - Y^3,
             // sin 6t = (gx gy/|g|^2)(6 X^2 - 20 X Y + 6 Y^2), and d cos(nt)/dg = n sin(nt)(gy,-gx)/|g|^2.
+            // Reciprocals use the hardware v_rcp_f32 (1 ulp); every operand is a normal number here.
             float a = 1.f, Nx = 0.f, Ny = 0.f;
             if (has_normal) {
-                const float inv = 1.f / (gx * gx + gy * gy);
+                const float inv = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
                 const float X = gx * gx * inv, Y = gy * gy * inv, XY = gx * gy * inv;
                 float Cn, Sn;
                 if (d.n_fold == 6) {
@@ -340,9 +419,9 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
             // ---- phase field, Eq. (d)/(e): relaxation eta = a^2 Dphi / cs^2 + 1/2, source Q / tau0
             const float a2 = a * a;
-            const float ia2 = 1.f / a2;
+            const float ia2 = __builtin_amdgcn_rcpf(a2);
             const float B = ia2 - 1.f;
-            const float ieta = 1.f / (3.f * d.Dphi * a2 + 0.5f);
+            const float ieta = __builtin_amdgcn_rcpf(3.f * d.Dphi * a2 + 0.5f);
             const float om = 1.f - phi * phi;
             const float srcQ = (phi - phi * phi * phi + d.lam * U * om * om) * d.inv_tau0;
 
@@ -361,7 +440,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 const float pc = fminf(fmaxf(phi, -1.f), 1.f);
                 const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
-                const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
+                const float sc = 0.5f * (1.f - pc) * __builtin_amdgcn_rcpf(rho + 0.5f * k);
                 ux = jx * sc;
                 uy = jy * sc;
                 const float Fx = -k * ux, Fy = -k * uy;
@@ -383,7 +462,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
             // ---- vapour (Sec. 2.2.2): tau_g = 1/2 + (tau_vap - 1/2) clamp((1 - phi)/2, 0, 1)
             const float sq = fminf(fmaxf(0.5f * (1.f - phi), 0.f), 1.f);
-            const float itg = 1.f / (0.5f + d.tauv_m_half * sq);
+            const float itg = __builtin_amdgcn_rcpf(0.5f + d.tauv_m_half * sq);
             const float srcg = d.half_Lsat * (phi - phip);
             float gs[5];
             {
@@ -410,53 +489,53 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             shq[0] = srcQ - sum8(shq);
 
             // ---- references this cell hands to the populations it emits (16-bit storage)
-            const int npar = 1 - par;
             float rU = 0.f, rR = 0.f, rJx = 0.f, rJy = 0.f;
             if (REF) {
-                typename S::T* wb = reinterpret_cast<typename S::T*>(d.refs[npar]);
-                const typename S::T tU = S::to_ref(U);
-                wb[cidx] = tU;
+                const T tU = S::to_ref(U);
+                gst<T>(rout, co * ES, tU);
                 rU = S::from_ref(tU);
                 if (FLOW) {
-                    const typename S::T tR = S::to_ref(rho), tX = S::to_ref(jx), tY = S::to_ref(jy);
-                    wb[d.rplane + cidx] = tR;
-                    wb[2 * d.rplane + cidx] = tX;
-                    wb[3 * d.rplane + cidx] = tY;
+                    const T tR = S::to_ref(rho), tX = S::to_ref(jx), tY = S::to_ref(jy);
+                    gst<T>(rout + rb, co * ES, tR);
+                    gst<T>(rout + 2 * rb, co * ES, tX);
+                    gst<T>(rout + 3 * rb, co * ES, tY);
                     rR = S::from_ref(tR);
                     rJx = S::from_ref(tX);
                     rJy = S::from_ref(tY);
                 }
             }
 
-            // ---- push streaming into copy 1 - par
+            // ---- push streaming into copy 1 - par (destination offsets: x part + y part)
             const int yN = (y + 1 < d.ny) ? y + 1 : 0;
             const int yS = (y > 0) ? y - 1 : d.ny - 1;
             const int xE = (x + 1 < d.nx) ? x + 1 : (INOUT ? -1 : 0);
             const int xW = (x > 0) ? x - 1 : (INOUT ? -1 : d.nx - 1);
+            const uint32_t xpE = cell_xpart(xE < 0 ? 0 : xE), xpW = cell_xpart(xW < 0 ? 0 : xW);
+            const uint32_t ypN = cell_ypart(d.nbx, yN), ypS = cell_ypart(d.nbx, yS);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
-                const int yd = CY[q] > 0 ? yN : (CY[q] < 0 ? yS : y);
+                const uint32_t ypd = CY[q] > 0 ? ypN : (CY[q] < 0 ? ypS : yp);
                 const float hs = h[q] - (h[q] - heq[q]) * ieta + shq[q];
                 const float Pq = hs * ia2;
                 const int lq = own + CY[q] * LX + CX[q];
                 const float fm = (REF && FLOW) ? f_ref(rR, rJx, rJy, CX[q], CY[q]) : 0.f;
                 if (xd >= 0) {
-                    const int64_t di = (int64_t)yd * d.pitch + xd;
+                    const uint32_t dO = ((CX[q] > 0 ? xpE : (CX[q] < 0 ? xpW : xp)) + ypd) * ES;
                     const float href = REF ? (float)s_phi[lq] : 0.f;  // h references its holder's phi(t)
-                    plane_ptr_w<S>(d, npar, d.off_h + q)[di] = S::enc(Pq - B * s_h[q][lq], IW9[q], href);
-                    if (FLOW) plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], fm);
-                    if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], rU);
+                    gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][lq], IW9[q], href));
+                    if (FLOW) gst<T>(pout + (PF + q) * pb, dO, S::enc(fs[q], IW9[q], fm));
+                    if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
                 }
                 if (INOUT) {
                     if (CX[q] < 0 && x == d.nx - 1) {
                         // outlet ghost at x = nx is a copy of this column: it streams into (nx-1, yd)
-                        const int64_t di = (int64_t)yd * d.pitch + x;
+                        const uint32_t dO = (xp + ypd) * ES;
                         const int ld = own + CY[q] * LX;
                         const float href = REF ? (float)s_phi[ld] : 0.f;
-                        plane_ptr_w<S>(d, npar, d.off_h + q)[di] = S::enc(Pq - B * s_h[q][ld], IW9[q], href);
-                        plane_ptr_w<S>(d, npar, q)[di] = S::enc(fs[q], IW9[q], fm);
-                        if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[di] = S::enc(gs[q], IW5[q], rU);
+                        gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][ld], IW9[q], href));
+                        gst<T>(pout + (PF + q) * pb, dO, S::enc(fs[q], IW9[q], fm));
+                        if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
                     }
                     if (CX[q] > 0 && x == 0) {
                         // inlet ghost at x = -1: equilibrium at (rho0, u_in; U_in; phi = -1); its
@@ -467,13 +546,13 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                             ggm = s_ref[R_U][lg];
                             gfm = f_ref(s_ref[R_RHO][lg], s_ref[R_JX][lg], s_ref[R_JY][lg], CX[q], CY[q]);
                         }
-                        plane_ptr_w<S>(d, npar, d.off_h + q)[cidx] = S::enc(-W9[q], IW9[q], REF ? phi : 0.f);
-                        plane_ptr_w<S>(d, npar, q)[cidx] = S::enc(d.f_in[q], IW9[q], gfm);
-                        if (q < 5) plane_ptr_w<S>(d, npar, d.off_g + q)[cidx] = S::enc(d.g_in[q], IW5[q], ggm);
+                        gst<T>(pout + (PH + q) * pb, co * ES, S::enc(-W9[q], IW9[q], REF ? phi : 0.f));
+                        gst<T>(pout + (PF + q) * pb, co * ES, S::enc(d.f_in[q], IW9[q], gfm));
+                        if (q < 5) gst<T>(pout + (PG + q) * pb, co * ES, S::enc(d.g_in[q], IW5[q], ggm));
                     }
                 }
             }
-            d.phip[npar][cidx] = phi;
+            gst<float>(phout, co * 4, phi);
         }
         __syncthreads();  // LDS is reused by the next tile
     }
@@ -614,10 +693,10 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
     const float rho0 = d.ref_f;
     float phi0, ux, U;
     init_at(d, a, x, y, phi0, ux, U);
-    const int64_t i = (int64_t)y * d.pitch + x;
-    d.phip[par][i] = phi0;
+    const int64_t i = cell_index(d.nbx, x, y);
+    phip_ptr(d, par)[i] = phi0;
     if (S::kLocalRef) {
-        typename S::T* wb = reinterpret_cast<typename S::T*>(d.refs[par]);
+        GMEM typename S::T* wb = (GMEM typename S::T*)(d.refs[par]);
         wb[i] = S::to_ref(U);
         if (flow) {
             wb[d.rplane + i] = S::to_ref(rho0);
@@ -730,7 +809,7 @@ __global__ void k_pop_get(DomDesc d, int par, int set, float* __restrict__ canon
     if (x >= d.nx || y >= d.ny) return;
     const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x;
     if (set == 3) {
-        canon[c] = d.phip[par][(int64_t)y * d.pitch + x];
+        canon[c] = phip_ptr(d, par)[cell_index(d.nbx, x, y)];
         return;
     }
     float f[9], g[5], h[9];
@@ -749,8 +828,8 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx || y >= d.ny) return;
-    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = (int64_t)y * d.pitch + x;
-    typename S::T* wb = S::kLocalRef ? reinterpret_cast<typename S::T*>(d.refs[par]) : nullptr;
+    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = cell_index(d.nbx, x, y);
+    GMEM typename S::T* wb = S::kLocalRef ? (GMEM typename S::T*)(d.refs[par]) : nullptr;
     if (set == 0 || set == 1) {
         if (S::kLocalRef) {
             if (set == 1) wb[i] = S::to_ref(0.f);
@@ -766,18 +845,18 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
                 plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], r[R_U]);
         }
     } else if (set == 2) {
-        const float ref = S::kLocalRef ? d.phip[par][i] : 0.f;
+        const float ref = S::kLocalRef ? phip_ptr(d, par)[i] : 0.f;
         for (int q = 0; q < 9; ++q) plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(canon[q * n + c], IW9[q], ref);
     } else {
         const float pnew = canon[c];
         if (S::kLocalRef) {
-            const float pold = d.phip[par][i];
+            const float pold = phip_ptr(d, par)[i];
             for (int q = 0; q < 9; ++q) {
-                typename S::T* p = plane_ptr_w<S>(d, par, d.off_h + q) + i;
+                GMEM typename S::T* p = plane_ptr_w<S>(d, par, d.off_h + q) + i;
                 *p = S::enc(S::dec(*p, W9[q], pold), IW9[q], pnew);
             }
         }
-        d.phip[par][i] = pnew;
+        phip_ptr(d, par)[i] = pnew;
     }
 }
 
@@ -847,7 +926,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DomDesc d, int par, doubl
                 jy += CY[q] * (double)f[q];
             }
         }
-        const float pp = d.phip[par][(int64_t)y * d.pitch + x];
+        const float pp = phip_ptr(d, par)[cell_index(d.nbx, x, y)];
         bad |= !isfinite(pp);
         acc[0] += rho; acc[1] += jx; acc[2] += jy; acc[3] += U; acc[4] += phi; acc[5] += pp;
         acc[6] += (phi > 0.0) ? 1.0 : 0.0;

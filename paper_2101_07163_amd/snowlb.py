@@ -12,7 +12,7 @@ import os
 from dataclasses import dataclass, fields
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libsnowlb.so")
+LIB_PATH = os.environ.get("SNOWLB_LIB") or os.path.join(HERE, "_lib", "libsnowlb.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
 STORE_FP32, STORE_FP16, STORE_BF16 = 0, 1, 2

@@ -97,3 +97,18 @@ def test_batch_rejects_mixed_kernels_before_gpu():
     assert S.lib().snowlb_batch_create(arr, 2, ctypes.byref(out)) == S.EINVAL
     assert "domain 0" in S.lib().snowlb_batch_last_error(None).decode()
     assert S.lib().snowlb_batch_create(arr, 0, ctypes.byref(out)) == S.EINVAL
+
+
+def test_lattice_size_limit():
+    """Every in-plane byte offset of the step kernel is 32-bit: a plane padded to whole 64 x 4 blocks
+    may hold at most 2^30 cells.  The limit is checked on the host, before any GPU call."""
+    p = S.snowlb_params_default()
+    p.nx, p.ny = 32768, 32768                 # exactly 2^30 cells
+    assert S.snowlb_validate(p) == (0, "")
+    p.ny = 32769                              # padded to 32772 rows: over the limit
+    st, msg = S.snowlb_validate(p)
+    assert st == S.EINVAL and "too large" in msg
+    p.nx, p.ny = 32705, 32768                 # padded to 32768 columns: still exactly 2^30
+    assert S.snowlb_validate(p) == (0, "")
+    p.nx, p.ny = 65537, 8
+    assert S.snowlb_validate(p)[0] == S.EINVAL
