@@ -33,9 +33,11 @@ __device__ constexpr float AW5[5] = {1.f / 3.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f,
 constexpr int ATX = 64, ATY = 4, ANT = ATX * ATY;
 constexpr int ALX = ATX + 2, ALY = ATY + 2, ALN = ALX * ALY;
 
+// i mod n for any i (one add or subtract in the common case: neighbours and halos of wide lattices)
 __device__ __forceinline__ int wrapn(int i, int n) {
     if (i < 0) i += n;
     if (i >= n) i -= n;
+    if ((unsigned)i >= (unsigned)n) i = ((i % n) + n) % n;
     return i;
 }
 
@@ -46,38 +48,90 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 }  // namespace
 
+// Position of LDS slot r of a tile at (x0, y0): the slots form the tile and its one-cell ring, row
+// by row (ALX x ALY); a lattice position outside the (periodic) lattice wraps.  Returns the in-plane
+// byte offset of that position.
+__device__ __forceinline__ uint32_t slot_off(const AdjDesc& A, int x0, int y0, int r) {
+    const int lx = r % ALX, ly = r / ALX;
+    const int gx = wrapn(x0 + lx - 1, A.nx), gy = wrapn(y0 + ly - 1, A.ny);
+    return (cell_xpart(gx) + cell_ypart(A.nbx, gy)) * 4u;
+}
+// LDS slots of the one-cell ring around a tile: top row, bottom row, left column, right column.
+__device__ __forceinline__ int ring_slot(int r) {
+    if (r < ALX) return r;
+    if (r < 2 * ALX) return (ALY - 1) * ALX + (r - ALX);
+    if (r < 2 * ALX + ATY) return (1 + r - 2 * ALX) * ALX;
+    return (1 + r - 2 * ALX - ATY) * ALX + ALX - 1;
+}
+constexpr int ARING = 2 * ALX + 2 * ATY;
+static_assert(ARING <= ANT, "one ring pass per workgroup");
+
 __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
     __shared__ double s_phi[ALN];
+    __shared__ float s_h[9][ALN];
     __shared__ double s_red[ANT / 64];
     const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
     const int ntx = (A.nx + ATX - 1) / ATX;
     const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < A.nx && y < A.ny;
-    const int64_t P = A.plane;
-    const float* hpl = A.st + 5 * P;  // h planes of the state
+    const int own = (ty + 1) * ALX + tx + 1;
+    const uint64_t pb = (uint64_t)A.plane * 4;  // bytes between planes
+    const GMEM char* st = (const GMEM char*)A.st;
+    const GMEM char* lin = (const GMEM char*)A.lin;
+    GMEM char* lout = (GMEM char*)A.lout;
+    GMEM char* mid = (GMEM char*)A.mid;
 
-    // phi(t) of the tile and its halo, summed in FP64 as in the forward step
-    for (int r = tid; r < ALN; r += ANT) {
-        const int lx = r % ALX, ly = r / ALX;
-        const int gx = ((x0 + lx - 1) % A.nx + A.nx) % A.nx, gy = ((y0 + ly - 1) % A.ny + A.ny) % A.ny;
-        const int64_t i = cell_index(A.nbx, gx, gy);
+    // h(t) and phi(t) of the tile and its ring in LDS, phi summed in FP64 as in the forward step.
+    // Lanes outside the lattice stage the position their slot wraps to (an active neighbour's halo).
+    const uint32_t oo = slot_off(A, x0, y0, own);
+    float h[9];
+    {
         double p = 0.0;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) p += (double)hpl[q * P + i];
+        for (int q = 0; q < 9; ++q) {
+            h[q] = gld<float>(st + (5 + q) * pb, oo);
+            p += (double)h[q];
+            s_h[q][own] = h[q];
+        }
+        s_phi[own] = p;
+    }
+    if (tid < ARING) {
+        const int r = ring_slot(tid);
+        const uint32_t ro = slot_off(A, x0, y0, r);
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const float v = gld<float>(st + (5 + q) * pb, ro);
+            p += (double)v;
+            s_h[q][r] = v;
+        }
         s_phi[r] = p;
+    }
+    // every other global load of this cell is issued before the barrier too: g(t), lambda(t + 1) of
+    // the populations it emitted (at x + c_q) and lambda_phiprev(t + 1)
+    const uint32_t xp = cell_xpart(x), yp = cell_ypart(A.nbx, y);
+    const uint32_t io = (xp + yp) * 4u;  // == oo for active lanes
+    const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
+    const uint32_t xpE = cell_xpart(xE), xpW = cell_xpart(xW);
+    const uint32_t ypN = cell_ypart(A.nbx, yN), ypS = cell_ypart(A.nbx, yS);
+    auto dest = [&](int q) -> uint32_t {
+        return ((AX[q] > 0 ? xpE : (AX[q] < 0 ? xpW : xp)) + (AY[q] > 0 ? ypN : (AY[q] < 0 ? ypS : yp))) * 4u;
+    };
+    float g[5], lh[9], lg[5], lpp = 0.f;
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) g[q] = gld<float>(st + q * pb, io);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) lh[q] = gld<float>(lin + (5 + q) * pb, dest(q));
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, dest(q));
+        lpp = gld<float>(lin + 14 * pb, io);
     }
     __syncthreads();
 
     double deps = 0.0;
     if (active) {
-        const int own = (ty + 1) * ALX + tx + 1;
-        const int64_t i = cell_index(A.nbx, x, y);
-        float h[9], g[5];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) h[q] = hpl[q * P + i];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) g[q] = A.st[q * P + i];
         const float phi = (float)s_phi[own];
         const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
 
@@ -89,7 +143,7 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
         const float gx = (float)gx64, gy = (float)gy64;
         float a = 1.f, Cn = 0.f, Sn = 0.f, c = 0.f, iG2 = 0.f;
         if (on) {
-            iG2 = 1.f / (gx * gx + gy * gy);
+            iG2 = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
             const float X = gx * gx * iG2, Y = gy * gy * iG2, XY = gx * gy * iG2;
             if (A.n_fold == 6) {
                 Cn = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
@@ -102,21 +156,17 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
             c = A.coefN * A.eps * a * Sn;
         }
         const float Nx = c * gy, Ny = -c * gx;
-        const float a2 = a * a, ia2 = 1.f / a2, B = ia2 - 1.f;
-        const float ie = 1.f / (3.f * A.Dphi * a2 + 0.5f);
+        const float a2 = a * a, ia2 = __builtin_amdgcn_rcpf(a2), B = ia2 - 1.f;
+        const float ie = __builtin_amdgcn_rcpf(3.f * A.Dphi * a2 + 0.5f);
         const float om = 1.f - phi * phi;
         const float Q = phi - phi * phi * phi + A.lam * U * om * om;
 
         // ---- reverse of the phase-field collision and push
         float ia2b = 0.f, Bb = 0.f, ieb = 0.f, Qb = 0.f, phb = 0.f, Nxb = 0.f, Nyb = 0.f;
-        const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
-            const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
-            const int64_t di = cell_index(A.nbx, xd, yd);
-            const float Pb = A.lin[(5 + q) * P + di];  // lambda_h,q(x + c_q, t + 1)
-            const float hold = hpl[q * P + di];         // h_q(x + c_q, t)
+            const float Pb = lh[q];                                   // lambda_h,q(x + c_q, t + 1)
+            const float hold = s_h[q][own + AY[q] * ALX + AX[q]];     // h_q(x + c_q, t)
             const float heq = AW9[q] * (phi - 3.f * (AX[q] * Nx + AY[q] * Ny));
             const float hs = h[q] - (h[q] - heq) * ie + AW9[q] * Q * A.inv_tau0;
             Bb -= Pb * hold;
@@ -151,28 +201,26 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
         // ---- reverse of the vapour collision and push
         const float qd = 0.5f * (1.f - phi);
         const bool inside = qd > 0.f && qd < 1.f;
-        const float itg = 1.f / (0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
+        const float itg = __builtin_amdgcn_rcpf(0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
         float itgb = 0.f, srcb = 0.f, gsb[5];
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-            const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
-            const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
-            gsb[q] = A.lin[q * P + cell_index(A.nbx, xd, yd)];
+            gsb[q] = lg[q];
             itgb -= gsb[q] * (g[q] - AW5[q] * U);
             Ub += AW5[q] * gsb[q] * itg;
             srcb -= AW5[q] * gsb[q];
         }
         phb += A.half_Lsat * srcb;
         if (inside) phb += -0.5f * A.tauv_m_half * (-itg * itg * itgb);
-        phb += A.lin[14 * P + i];  // phi_prev(t + 1) = phi(t)
+        phb += lpp;  // phi_prev(t + 1) = phi(t)
 #pragma unroll
-        for (int q = 0; q < 5; ++q) A.lout[q * P + i] = gsb[q] * (1.f - itg) + Ub;
-        A.lout[14 * P + i] = -A.half_Lsat * srcb;
-        A.mid[0 * P + i] = ia2 * (1.f - ie);
-        A.mid[1 * P + i] = B;
-        A.mid[2 * P + i] = Gxb;
-        A.mid[3 * P + i] = Gyb;
-        A.mid[4 * P + i] = phb;
+        for (int q = 0; q < 5; ++q) gst<float>(lout + q * pb, io, gsb[q] * (1.f - itg) + Ub);
+        gst<float>(lout + 14 * pb, io, -A.half_Lsat * srcb);
+        gst<float>(mid + 0 * pb, io, ia2 * (1.f - ie));
+        gst<float>(mid + 1 * pb, io, B);
+        gst<float>(mid + 2 * pb, io, Gxb);
+        gst<float>(mid + 3 * pb, io, Gyb);
+        gst<float>(mid + 4 * pb, io, phb);
     }
     // fixed-order workgroup reduction of the eps contribution
     const double w = wave_sum_d(deps);
@@ -185,31 +233,61 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
     }
 }
 
-__global__ void __launch_bounds__(256) k_adj_b(AdjDesc A) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
-    if (x >= A.nx || y >= A.ny) return;
-    const int64_t P = A.plane, i = cell_index(A.nbx, x, y);
+__global__ void __launch_bounds__(ANT) k_adj_b(AdjDesc A) {
+    // B, Gbar_x, Gbar_y of the tile and its ring in LDS (gathered at x - c_q and x - c_k)
+    __shared__ float s_B[ALN], s_Gx[ALN], s_Gy[ALN];
+    const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
+    const int ntx = (A.nx + ATX - 1) / ATX;
+    const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < A.nx && y < A.ny;
+    const int own = (ty + 1) * ALX + tx + 1;
+    const uint64_t pb = (uint64_t)A.plane * 4;
+    const GMEM char* lin = (const GMEM char*)A.lin;
+    GMEM char* lout = (GMEM char*)A.lout;
+    const GMEM char* mid = (const GMEM char*)A.mid;
+    {
+        const uint32_t oo = slot_off(A, x0, y0, own);
+        s_B[own] = gld<float>(mid + 1 * pb, oo);
+        s_Gx[own] = gld<float>(mid + 2 * pb, oo);
+        s_Gy[own] = gld<float>(mid + 3 * pb, oo);
+    }
+    if (tid < ARING) {
+        const int r = ring_slot(tid);
+        const uint32_t ro = slot_off(A, x0, y0, r);
+        s_B[r] = gld<float>(mid + 1 * pb, ro);
+        s_Gx[r] = gld<float>(mid + 2 * pb, ro);
+        s_Gy[r] = gld<float>(mid + 3 * pb, ro);
+    }
+    // the cell's own global loads are issued before the barrier too
+    const uint32_t xp = cell_xpart(x), yp = cell_ypart(A.nbx, y);
+    const uint32_t io = (xp + yp) * 4u;
     const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
-    float phb = A.mid[4 * P + i];
+    const uint32_t xpE = cell_xpart(xE), xpW = cell_xpart(xW);
+    const uint32_t ypN = cell_ypart(A.nbx, yN), ypS = cell_ypart(A.nbx, yS);
+    float phb = 0.f, Ah = 0.f, ld[9], lo[9];
+    if (active) {
+        phb = gld<float>(mid + 4 * pb, io);
+        Ah = gld<float>(mid + 0 * pb, io);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const uint32_t dO = ((AX[q] > 0 ? xpE : (AX[q] < 0 ? xpW : xp)) + (AY[q] > 0 ? ypN : (AY[q] < 0 ? ypS : yp))) * 4u;
+            ld[q] = gld<float>(lin + (5 + q) * pb, dO);  // lambda_h,q(x + c_q, t + 1)
+            lo[q] = gld<float>(lin + (5 + q) * pb, io);  // lambda_h,q(x, t + 1)
+        }
+    }
+    __syncthreads();
+    if (!active) return;
 #pragma unroll
     for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
-        const int xs = AX[k] > 0 ? xW : (AX[k] < 0 ? xE : x);
-        const int ys = AY[k] > 0 ? yS : (AY[k] < 0 ? yN : y);
-        const int64_t j = cell_index(A.nbx, xs, ys);
+        const int j = own - AY[k] * ALX - AX[k];
         const float w = (k < 5) ? (1.f / 3.f) : (1.f / 12.f);
-        phb += w * (AX[k] * A.mid[2 * P + j] + AY[k] * A.mid[3 * P + j]);
+        phb += w * (AX[k] * s_Gx[j] + AY[k] * s_Gy[j]);
     }
-    const float Ah = A.mid[0 * P + i];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        const int xd = AX[q] > 0 ? xE : (AX[q] < 0 ? xW : x);
-        const int yd = AY[q] > 0 ? yN : (AY[q] < 0 ? yS : y);
-        const int xu = AX[q] > 0 ? xW : (AX[q] < 0 ? xE : x);
-        const int yu = AY[q] > 0 ? yS : (AY[q] < 0 ? yN : y);
-        const float ld = A.lin[(5 + q) * P + cell_index(A.nbx, xd, yd)];
-        const float lo = A.lin[(5 + q) * P + i];
-        const float Bu = A.mid[1 * P + cell_index(A.nbx, xu, yu)];
-        A.lout[(5 + q) * P + i] = ld * Ah - Bu * lo + phb;
+        const float Bu = s_B[own - AY[q] * ALX - AX[q]];
+        gst<float>(lout + (5 + q) * pb, io, ld[q] * Ah - Bu * lo[q] + phb);
     }
 }
 
@@ -270,7 +348,7 @@ hipError_t launch_adj_step(const AdjDesc& A, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_a, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_b, dim3((A.nx + 255) / 256, A.ny), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_adj_b, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
     return hipGetLastError();
 }
 

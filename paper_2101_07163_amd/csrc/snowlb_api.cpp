@@ -366,6 +366,13 @@ struct snowlb_ctx {
         double* h_out = nullptr;  // pinned, 2 doubles
         DomDesc* d_segdoms = nullptr;
         int nsegdoms = 0;
+        // captured segment programs (the recompute and reverse steps of one checkpoint interval),
+        // each keyed by every value its kernel arguments bake in
+        struct SegGraph {
+            std::vector<char> key;
+            hipGraphExec_t exec = nullptr;
+        };
+        std::vector<SegGraph> graphs;
     } adj;
 };
 
@@ -477,7 +484,14 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     return SNOWLB_OK;
 }
 
+void adj_drop_graphs(snowlb_ctx* c) {
+    for (auto& g : c->adj.graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->adj.graphs.clear();
+}
+
 void adj_free(snowlb_ctx* c) {
+    adj_drop_graphs(c);
     if (c->adj.slots) (void)hipFree(c->adj.slots);
     if (c->adj.buf) (void)hipFree(c->adj.buf);
     if (c->adj.epart) (void)hipFree(c->adj.epart);
@@ -868,6 +882,74 @@ snowlb_status snowlb_adj_forward(snowlb_ctx* c, int32_t n, int32_t stride, void*
     return SNOWLB_OK;
 }
 
+// The captured program of one checkpoint interval of length len whose reverse steps start reading
+// lambda[cur]: (len - 1) recompute steps through the segment descriptors, then len reverse steps.
+// Programs are cached on the context, keyed by every value their kernel arguments bake in.
+static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const lam[2], int len, int cur, int grid,
+                                       hipGraphExec_t* out) {
+    Driver& D = c->drv;
+    struct Key {
+        AdjDesc A;
+        const void* lam0;
+        const void* lam1;
+        const void* slots;
+        const void* segdoms;
+        const void* tiles;
+        int64_t slot_bytes;
+        int32_t nck, tile, grid, storage, len, cur;
+    } key;
+    std::memset(&key, 0, sizeof key);
+    key.A = A;
+    key.A.st = key.A.lin = nullptr;
+    key.A.lout = nullptr;
+    key.lam0 = lam[0];
+    key.lam1 = lam[1];
+    key.slots = c->adj.slots;
+    key.segdoms = c->adj.d_segdoms;
+    key.tiles = D.d_tiles[D.tile];
+    key.slot_bytes = c->adj.slot_bytes;
+    key.nck = c->adj.nck;
+    key.tile = D.tile;
+    key.grid = grid;
+    key.storage = c->p.storage;
+    key.len = len;
+    key.cur = cur;
+    const char* kb = reinterpret_cast<const char*>(&key);
+    for (auto& sg : c->adj.graphs)
+        if (sg.key.size() == sizeof key && std::memcmp(sg.key.data(), kb, sizeof key) == 0) {
+            *out = sg.exec;
+            return SNOWLB_OK;
+        }
+    if (c->adj.graphs.size() >= 8) adj_drop_graphs(c);
+    hipStream_t cs = D.cap_stream;
+    HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int i = 0; i + 1 < len && le == hipSuccess; ++i)
+        le = launch_step(D.tile, c->p.storage, 0, 0, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid,
+                         0, cs);
+    for (int i = len - 1; i >= 0 && le == hipSuccess; --i) {
+        A.st = (const float*)adj_slot(c, c->adj.nck + i);
+        A.lin = lam[cur];
+        A.lout = lam[1 - cur];
+        le = launch_adj_step(A, cs);
+        cur ^= 1;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(c, le, "adjoint segment capture");
+    }
+    if (ee != hipSuccess) return hip_fail(c, ee, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return hip_fail(c, ie, "hipGraphInstantiate");
+    c->adj.graphs.push_back({std::vector<char>(kb, kb + sizeof key), ex});
+    *out = ex;
+    return SNOWLB_OK;
+}
+
 snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, double* deps, double* dU0,
                                   void* stream) {
     if (!c) return SNOWLB_EINVAL;
@@ -926,24 +1008,18 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     snowlb_status r = from_driver(c, D.ensure_tiles(D.tile));
     if (r) return r;
     const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, D.grid_mode);
+    // Each checkpoint interval: copy its checkpoint into the first segment slot, then replay the
+    // captured program of (len - 1) recompute steps and len reverse steps.  At most three distinct
+    // programs occur (the shorter last interval, and a full one for each parity of lambda).
     int cur = 0;
     for (int k = c->adj.nck - 1; k >= 0; --k) {
         const int len = std::min(st, n - k * st);
         HIPCHK(c, hipMemcpyAsync(adj_slot(c, c->adj.nck), adj_slot(c, k), (size_t)c->adj.slot_bytes,
                                  hipMemcpyDeviceToDevice, s));
-        for (int i = 0; i + 1 < len; ++i) {
-            e = launch_step(D.tile, c->p.storage, 0, 0, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile],
-                            grid, 0, s);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint recompute step");
-        }
-        for (int i = len - 1; i >= 0; --i) {
-            A.st = (const float*)adj_slot(c, c->adj.nck + i);
-            A.lin = lam[cur];
-            A.lout = lam[1 - cur];
-            e = launch_adj_step(A, s);
-            if (e != hipSuccess) return hip_fail(c, e, "adjoint step kernels");
-            cur ^= 1;
-        }
+        hipGraphExec_t g = nullptr;
+        if (snowlb_status r2 = adj_segment_graph(c, A, lam, len, cur, grid, &g)) return r2;
+        HIPCHK(c, hipGraphLaunch(g, s));
+        cur ^= len & 1;
     }
     A.lin = lam[cur];
     e = launch_adj_finish(A, dU, c->adj.rows, c->adj.d_out, s);

@@ -32,6 +32,21 @@ __host__ __device__ __forceinline__ int64_t cell_index(int nbx, int x, int y) {
     return (int64_t)cell_ypart(nbx, y) + cell_xpart(x);
 }
 
+// Global accesses of the hot kernels: a base that is uniform over the workgroup plus a 32-bit
+// per-lane byte offset.  The empty asm pins the base in scalar registers and keeps the compiler from
+// folding a plane stride into a 64-bit per-lane address, so each access is one global load or store
+// in scalar-base + vector-offset form (every caller passes a workgroup-uniform base).
+template <class T>
+__device__ __forceinline__ T gld(const GMEM char* base, uint32_t boff) {
+    asm("" : "+s"(base));
+    return *(const GMEM T*)(base + boff);
+}
+template <class T>
+__device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
+    asm("" : "+s"(base));
+    *(GMEM T*)(base + boff) = v;
+}
+
 struct DomDesc {
     int32_t nx, ny, nbx, npop;    // nbx: 64 x 4 blocks per block row; npop: planes per copy (23 with
                                   // flow, 14 without)

@@ -139,21 +139,6 @@ __device__ __forceinline__ bool map_off(const DomDesc& d, int gx, int gy, uint32
     return true;
 }
 
-// Global accesses of the step: a base that is uniform over the workgroup plus a 32-bit per-lane
-// byte offset.  The empty asm pins the base in scalar registers and keeps the compiler from folding
-// the plane stride into a 64-bit per-lane address, so each access is one global load or store in
-// scalar-base + vector-offset form (every caller passes a workgroup-uniform base).
-template <class T>
-__device__ __forceinline__ T gld(const GMEM char* base, uint32_t boff) {
-    asm("" : "+s"(base));
-    return *(const GMEM T*)(base + boff);
-}
-template <class T>
-__device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
-    asm("" : "+s"(base));
-    *(GMEM T*)(base + boff) = v;
-}
-
 // Reference values (U, rho, jx, jy) of lattice position (gx, gy) with the closure: the inlet ghost
 // carries (U_in, rho0, rho0 u_in, 0) rounded to the storage format.
 template <class S>
