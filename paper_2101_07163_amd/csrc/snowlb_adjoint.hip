@@ -2,20 +2,21 @@
 //
 // For a loss L(phi_T), the adjoint lambda_t = dL/d(state at t) obeys lambda_t = (dF/ds)^T lambda_{t+1}
 // where F is one step of the phase field (Eq. (d)/(e), anisotropy of Sec. 2.1, E4 gradient of
-// Table 1) and the vapour ADR solver (Sec. 2.2.2) with u = 0.  Each reverse step is two gather
-// kernels over the lattice:
-//   k_adj_a (per cell x): recompute the forward quantities of x from the stored state at t (phi with
-//     its halo for the gradient, a, N, eta, Q, h_eq, h*), take lambda_{t+1} of the populations x
-//     emitted (at x + c_q), and form every adjoint that is local to x: lambda_g(x, t) and
-//     lambda_phiprev(x, t) completely, and for the h adjoint the per-cell factors A_h = (1 - 1/eta)/a^2,
-//     B = (1 - a^2)/a^2, the adjoint of the gradient Gbar(x) and the local part of phibar(x); the
-//     explicit dependence on eps is reduced into per-workgroup FP64 partials.
-//   k_adj_b (per cell x): lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x)   [through h*_q(x)]
-//                                           - B(x - c_q) lambda_h,q(x)      [destination term of Eq. (d)]
-//                                           + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)   [phi = sum h]
+// Table 1) and the vapour ADR solver (Sec. 2.2.2) with u = 0.  Each reverse step is one kernel,
+// k_adj, over 64 x 4 tiles, in two passes:
+//   pass A (per position p of the tile and of its one-cell ring): recompute the forward quantities of
+//     p from the stored state at t (phi with its halo for the gradient, a, N, eta, Q, h_eq, h*), take
+//     lambda_{t+1} of the populations p emitted (at p + c_q), and form every adjoint that is local to
+//     p: lambda_g(p, t) and lambda_phiprev(p, t) completely, and for the h adjoint the per-cell
+//     factors A_h = (1 - 1/eta)/a^2, B = (1 - a^2)/a^2, the adjoint of the gradient Gbar(p) and the
+//     local part of phibar(p); the explicit dependence on eps is reduced into per-workgroup FP64
+//     partials (tile cells only);
+//   pass B (per cell x of the tile): lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x)   [through h*_q(x)]
+//                                     - B(x - c_q) lambda_h,q(x)      [destination term of Eq. (d)]
+//                                     + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)   [phi = sum h]
+//     with B and Gbar of the neighbours taken from LDS.
 // Layout: every field is an FP32 plane in the cell order of the state, with the state's plane stride;
-// the state slot holds g_0..4 then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev; the
-// intermediate slot holds A_h, B, Gbar_x, Gbar_y, phibar.
+// the state slot holds g_0..4 then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -48,14 +49,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 }
 }  // namespace
 
-// Position of LDS slot r of a tile at (x0, y0): the slots form the tile and its one-cell ring, row
-// by row (ALX x ALY); a lattice position outside the (periodic) lattice wraps.  Returns the in-plane
-// byte offset of that position.
-__device__ __forceinline__ uint32_t slot_off(const AdjDesc& A, int x0, int y0, int r) {
-    const int lx = r % ALX, ly = r / ALX;
-    const int gx = wrapn(x0 + lx - 1, A.nx), gy = wrapn(y0 + ly - 1, A.ny);
-    return (cell_xpart(gx) + cell_ypart(A.nbx, gy)) * 4u;
-}
 // LDS slots of the one-cell ring around a tile: top row, bottom row, left column, right column.
 __device__ __forceinline__ int ring_slot(int r) {
     if (r < ALX) return r;
@@ -63,165 +56,241 @@ __device__ __forceinline__ int ring_slot(int r) {
     if (r < 2 * ALX + ATY) return (1 + r - 2 * ALX) * ALX;
     return (1 + r - 2 * ALX - ATY) * ALX + ALX - 1;
 }
-constexpr int ARING = 2 * ALX + 2 * ATY;
-static_assert(ARING <= ANT, "one ring pass per workgroup");
+// One reverse step is one kernel over 64 x 4 tiles.  Pass B at a cell gathers B(x - c_q) and
+// Gbar(x - c_k) from pass A at its eight neighbours, so each workgroup runs pass A on its tile and
+// on the one-cell ring around it (the ring positions recomputed by both neighbouring workgroups
+// from the same inputs with the same code, hence bitwise equal), which needs h and phi on a two-cell
+// ring.  No intermediate plane goes through memory.
+constexpr int L2X = ATX + 4, L2Y = ATY + 4, L2N = L2X * L2Y;  // staging region: tile + two rings
+constexpr int RING1 = 2 * ALX + 2 * ATY;                     // the one-cell ring
+static_assert(RING1 <= ANT, "one ring position per lane");
 
-__global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
-    __shared__ double s_phi[ALN];
-    __shared__ float s_h[9][ALN];
+// Byte offsets of a lattice position (wrapped into the periodic lattice) and of its eight
+// neighbours, as separable x and y parts.
+struct Nb {
+    uint32_t xp, xE, xW, yp, yN, yS;
+    __device__ __forceinline__ uint32_t at() const { return (xp + yp) * 4u; }
+    __device__ __forceinline__ uint32_t dest(int q) const {
+        return ((AX[q] > 0 ? xE : (AX[q] < 0 ? xW : xp)) + (AY[q] > 0 ? yN : (AY[q] < 0 ? yS : yp))) * 4u;
+    }
+};
+__device__ __forceinline__ Nb nb_of(const AdjDesc& A, int gx, int gy) {
+    Nb n;
+    n.xp = cell_xpart(wrapn(gx, A.nx));
+    n.xE = cell_xpart(wrapn(gx + 1, A.nx));
+    n.xW = cell_xpart(wrapn(gx - 1, A.nx));
+    n.yp = cell_ypart(A.nbx, wrapn(gy, A.ny));
+    n.yN = cell_ypart(A.nbx, wrapn(gy + 1, A.ny));
+    n.yS = cell_ypart(A.nbx, wrapn(gy - 1, A.ny));
+    return n;
+}
+
+// Pass A at one position p: recompute the forward quantities of p from the staged h and phi (slot
+// c2 of the staging region), then reverse the phase-field collision and push.  Always gives B(p) and
+// Gbar(p); with FULL also reverses the vapour collision and push and gives lambda_g(p, t) (lgo),
+// lambda_phiprev(p, t) (lppo), A_h(p), the local part of phibar(p) and the eps contribution of p.
+template <bool FULL>
+__device__ __forceinline__ void pass_a(const AdjDesc& A, const double* s_phi, const float (*s_h)[L2N], int c2,
+                                       const float g[5], const float lh[9], const float lg[5], float lpp,
+                                       float& Bv, float& Gxb, float& Gyb, float& Ah, float& phb, double& deps,
+                                       float lgo[5], float& lppo) {
+    float h[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) h[q] = s_h[q][c2];
+    const float phi = (float)s_phi[c2];
+    const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+
+    // ---- forward recompute (as the step kernel)
+    const double* S = s_phi + c2;
+    const double gx64 = (1.0 / 3.0) * (S[1] - S[-1]) + (1.0 / 12.0) * ((S[L2X + 1] - S[L2X - 1]) + (S[-L2X + 1] - S[-L2X - 1]));
+    const double gy64 = (1.0 / 3.0) * (S[L2X] - S[-L2X]) + (1.0 / 12.0) * ((S[L2X + 1] + S[L2X - 1]) - (S[-L2X + 1] + S[-L2X - 1]));
+    const bool on = gx64 * gx64 + gy64 * gy64 > A.grad_eps2;
+    const float gx = (float)gx64, gy = (float)gy64;
+    float a = 1.f, Cn = 0.f, Sn = 0.f, c = 0.f, iG2 = 0.f;
+    if (on) {
+        iG2 = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
+        const float X = gx * gx * iG2, Y = gy * gy * iG2, XY = gx * gy * iG2;
+        if (A.n_fold == 6) {
+            Cn = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
+            Sn = XY * (6.f * X * X - 20.f * X * Y + 6.f * Y * Y);
+        } else {
+            Cn = X * X - 6.f * X * Y + Y * Y;
+            Sn = XY * 4.f * (X - Y);
+        }
+        a = 1.f + A.eps * Cn;
+        c = A.coefN * A.eps * a * Sn;
+    }
+    const float Nx = c * gy, Ny = -c * gx;
+    const float a2 = a * a, ia2 = __builtin_amdgcn_rcpf(a2), B = ia2 - 1.f;
+    const float ie = __builtin_amdgcn_rcpf(3.f * A.Dphi * a2 + 0.5f);
+    const float om = 1.f - phi * phi;
+    const float Q = phi - phi * phi * phi + A.lam * U * om * om;
+
+    // ---- reverse of the phase-field collision and push
+    float ia2b = 0.f, Bb = 0.f, ieb = 0.f, Qb = 0.f, pb_ = 0.f, Nxb = 0.f, Nyb = 0.f;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const float Pb = lh[q];                          // lambda_h,q(p + c_q, t + 1)
+        const float hold = s_h[q][c2 + AY[q] * L2X + AX[q]];  // h_q(p + c_q, t)
+        const float heq = AW9[q] * (phi - 3.f * (AX[q] * Nx + AY[q] * Ny));
+        const float hs = h[q] - (h[q] - heq) * ie + AW9[q] * Q * A.inv_tau0;
+        Bb -= Pb * hold;
+        ia2b += Pb * hs;
+        const float hsb = Pb * ia2;
+        ieb += hsb * (heq - h[q]);
+        const float heqb = hsb * ie;
+        Qb += hsb * AW9[q] * A.inv_tau0;
+        pb_ += AW9[q] * heqb;
+        Nxb -= 3.f * AW9[q] * heqb * AX[q];
+        Nyb -= 3.f * AW9[q] * heqb * AY[q];
+    }
+    pb_ += Qb * (1.f - 3.f * phi * phi - 4.f * A.lam * U * phi * om);
+    float Ub = Qb * A.lam * om * om;
+    ia2b += Bb;
+    const float a2b = -ia2 * ia2 * ia2b + 3.f * A.Dphi * (-ie * ie * ieb);
+    float ab = 2.f * a * a2b;
+    Gxb = 0.f;
+    Gyb = 0.f;
+    if (on) {
+        const float cb = gy * Nxb - gx * Nyb;  // N = c (gy, -gx)
+        Gxb += -c * Nyb;
+        Gyb += c * Nxb;
+        ab += A.coefN * A.eps * Sn * cb;
+        const float Sb = A.coefN * A.eps * a * cb;
+        if (FULL) deps = (double)(Cn * ab) + (double)(A.coefN * a * Sn * cb);
+        const float Cb = A.eps * ab;
+        const float m = (float)A.n_fold;
+        Gxb += (Cb * m * Sn * gy - Sb * m * Cn * gy) * iG2;
+        Gyb += (-Cb * m * Sn * gx + Sb * m * Cn * gx) * iG2;
+    }
+    Bv = B;
+    if (!FULL) return;
+
+    // ---- reverse of the vapour collision and push
+    const float qd = 0.5f * (1.f - phi);
+    const bool inside = qd > 0.f && qd < 1.f;
+    const float itg = __builtin_amdgcn_rcpf(0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
+    float itgb = 0.f, srcb = 0.f;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        itgb -= lg[q] * (g[q] - AW5[q] * U);
+        Ub += AW5[q] * lg[q] * itg;
+        srcb -= AW5[q] * lg[q];
+    }
+    pb_ += A.half_Lsat * srcb;
+    if (inside) pb_ += -0.5f * A.tauv_m_half * (-itg * itg * itgb);
+    pb_ += lpp;  // phi_prev(t + 1) = phi(t)
+#pragma unroll
+    for (int q = 0; q < 5; ++q) lgo[q] = lg[q] * (1.f - itg) + Ub;
+    lppo = -A.half_Lsat * srcb;
+    Ah = ia2 * (1.f - ie);
+    phb = pb_;
+}
+
+__global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
+    __shared__ double s_phi[L2N];
+    __shared__ float s_h[9][L2N];
+    __shared__ float s_B[ALN], s_Gx[ALN], s_Gy[ALN];
     __shared__ double s_red[ANT / 64];
     const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
     const int ntx = (A.nx + ATX - 1) / ATX;
     const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < A.nx && y < A.ny;
-    const int own = (ty + 1) * ALX + tx + 1;
     const uint64_t pb = (uint64_t)A.plane * 4;  // bytes between planes
     const GMEM char* st = (const GMEM char*)A.st;
     const GMEM char* lin = (const GMEM char*)A.lin;
     GMEM char* lout = (GMEM char*)A.lout;
-    GMEM char* mid = (GMEM char*)A.mid;
 
-    // h(t) and phi(t) of the tile and its ring in LDS, phi summed in FP64 as in the forward step.
-    // Lanes outside the lattice stage the position their slot wraps to (an active neighbour's halo).
-    const uint32_t oo = slot_off(A, x0, y0, own);
-    float h[9];
-    {
-        double p = 0.0;
+    // ---- global loads, all issued before the barrier.  This lane's own position (wrapped into the
+    // lattice for lanes outside it: their slots are halo of active neighbours) ...
+    const Nb on = nb_of(A, x, y);
+    float g[5], lh[9], lg[5] = {}, lo[9] = {}, lpp = 0.f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            h[q] = gld<float>(st + (5 + q) * pb, oo);
-            p += (double)h[q];
-            s_h[q][own] = h[q];
-        }
-        s_phi[own] = p;
+    for (int q = 0; q < 5; ++q) g[q] = gld<float>(st + q * pb, on.at());
+#pragma unroll
+    for (int q = 0; q < 9; ++q) lh[q] = gld<float>(lin + (5 + q) * pb, on.dest(q));
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, on.dest(q));
+        lpp = gld<float>(lin + 14 * pb, on.at());
+#pragma unroll
+        for (int q = 0; q < 9; ++q) lo[q] = gld<float>(lin + (5 + q) * pb, on.at());
     }
-    if (tid < ARING) {
-        const int r = ring_slot(tid);
-        const uint32_t ro = slot_off(A, x0, y0, r);
+    // ... one position of the one-cell ring (pass A there needs g and lambda_h(t + 1) only) ...
+    const bool has_ring = tid < RING1;
+    const int r1 = has_ring ? ring_slot(tid) : 0;  // slot in the (ALX x ALY) pass-A region
+    const Nb rn = nb_of(A, x0 + r1 % ALX - 1, y0 + r1 / ALX - 1);
+    float rg[5], rlh[9];
+    if (has_ring) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rg[q] = gld<float>(st + q * pb, rn.at());
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rlh[q] = gld<float>(lin + (5 + q) * pb, rn.dest(q));
+    }
+    // ... and h(t) with phi(t) = sum h (FP64, as in the forward step) on the tile and two rings
+    for (int r = tid; r < L2N; r += ANT) {
+        const int lx = r % L2X, ly = r / L2X;
+        const uint32_t o = (cell_xpart(wrapn(x0 + lx - 2, A.nx)) + cell_ypart(A.nbx, wrapn(y0 + ly - 2, A.ny))) * 4u;
         double p = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const float v = gld<float>(st + (5 + q) * pb, ro);
+            const float v = gld<float>(st + (5 + q) * pb, o);
             p += (double)v;
             s_h[q][r] = v;
         }
         s_phi[r] = p;
     }
-    // every other global load of this cell is issued before the barrier too: g(t), lambda(t + 1) of
-    // the populations it emitted (at x + c_q) and lambda_phiprev(t + 1)
-    const uint32_t xp = cell_xpart(x), yp = cell_ypart(A.nbx, y);
-    const uint32_t io = (xp + yp) * 4u;  // == oo for active lanes
-    const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
-    const uint32_t xpE = cell_xpart(xE), xpW = cell_xpart(xW);
-    const uint32_t ypN = cell_ypart(A.nbx, yN), ypS = cell_ypart(A.nbx, yS);
-    auto dest = [&](int q) -> uint32_t {
-        return ((AX[q] > 0 ? xpE : (AX[q] < 0 ? xpW : xp)) + (AY[q] > 0 ? ypN : (AY[q] < 0 ? ypS : yp))) * 4u;
-    };
-    float g[5], lh[9], lg[5], lpp = 0.f;
-    if (active) {
+    __syncthreads();
+
+    // ---- pass A on the tile (every lane, at its wrapped position) and on the ring
+    double deps = 0.0;
+    float Ah = 0.f, phb = 0.f;
+    {
+        const int c2 = (ty + 2) * L2X + tx + 2, c1 = (ty + 1) * ALX + tx + 1;
+        float lgo[5], lppo = 0.f, Bv, Gx, Gy;
+        pass_a<true>(A, s_phi, s_h, c2, g, lh, lg, lpp, Bv, Gx, Gy, Ah, phb, deps, lgo, lppo);
+        s_B[c1] = Bv;
+        s_Gx[c1] = Gx;
+        s_Gy[c1] = Gy;
+        if (active) {
+            const uint32_t io = on.at();
 #pragma unroll
-        for (int q = 0; q < 5; ++q) g[q] = gld<float>(st + q * pb, io);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) lh[q] = gld<float>(lin + (5 + q) * pb, dest(q));
-#pragma unroll
-        for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, dest(q));
-        lpp = gld<float>(lin + 14 * pb, io);
+            for (int q = 0; q < 5; ++q) gst<float>(lout + q * pb, io, lgo[q]);
+            gst<float>(lout + 14 * pb, io, lppo);
+        } else {
+            deps = 0.0;
+        }
+    }
+    if (has_ring) {
+        const int c2 = (r1 / ALX + 1) * L2X + r1 % ALX + 1;
+        float Bv, Gx, Gy, ah_, ph_, lgo[5], lppo;
+        double de_ = 0.0;
+        pass_a<false>(A, s_phi, s_h, c2, rg, rlh, rg, 0.f, Bv, Gx, Gy, ah_, ph_, de_, lgo, lppo);
+        s_B[r1] = Bv;
+        s_Gx[r1] = Gx;
+        s_Gy[r1] = Gy;
     }
     __syncthreads();
 
-    double deps = 0.0;
+    // ---- pass B: lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x) - B(x - c_q) lambda_h,q(x)
+    //                                + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)
     if (active) {
-        const float phi = (float)s_phi[own];
-        const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
-
-        // ---- forward recompute (as the step kernel)
-        const double* S = s_phi + own;
-        const double gx64 = (1.0 / 3.0) * (S[1] - S[-1]) + (1.0 / 12.0) * ((S[ALX + 1] - S[ALX - 1]) + (S[-ALX + 1] - S[-ALX - 1]));
-        const double gy64 = (1.0 / 3.0) * (S[ALX] - S[-ALX]) + (1.0 / 12.0) * ((S[ALX + 1] + S[ALX - 1]) - (S[-ALX + 1] + S[-ALX - 1]));
-        const bool on = gx64 * gx64 + gy64 * gy64 > A.grad_eps2;
-        const float gx = (float)gx64, gy = (float)gy64;
-        float a = 1.f, Cn = 0.f, Sn = 0.f, c = 0.f, iG2 = 0.f;
-        if (on) {
-            iG2 = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
-            const float X = gx * gx * iG2, Y = gy * gy * iG2, XY = gx * gy * iG2;
-            if (A.n_fold == 6) {
-                Cn = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
-                Sn = XY * (6.f * X * X - 20.f * X * Y + 6.f * Y * Y);
-            } else {
-                Cn = X * X - 6.f * X * Y + Y * Y;
-                Sn = XY * 4.f * (X - Y);
-            }
-            a = 1.f + A.eps * Cn;
-            c = A.coefN * A.eps * a * Sn;
+        const int own = (ty + 1) * ALX + tx + 1;
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
+            const int j = own - AY[k] * ALX - AX[k];
+            const float w = (k < 5) ? (1.f / 3.f) : (1.f / 12.f);
+            phb += w * (AX[k] * s_Gx[j] + AY[k] * s_Gy[j]);
         }
-        const float Nx = c * gy, Ny = -c * gx;
-        const float a2 = a * a, ia2 = __builtin_amdgcn_rcpf(a2), B = ia2 - 1.f;
-        const float ie = __builtin_amdgcn_rcpf(3.f * A.Dphi * a2 + 0.5f);
-        const float om = 1.f - phi * phi;
-        const float Q = phi - phi * phi * phi + A.lam * U * om * om;
-
-        // ---- reverse of the phase-field collision and push
-        float ia2b = 0.f, Bb = 0.f, ieb = 0.f, Qb = 0.f, phb = 0.f, Nxb = 0.f, Nyb = 0.f;
+        const uint32_t io = on.at();
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-            const float Pb = lh[q];                                   // lambda_h,q(x + c_q, t + 1)
-            const float hold = s_h[q][own + AY[q] * ALX + AX[q]];     // h_q(x + c_q, t)
-            const float heq = AW9[q] * (phi - 3.f * (AX[q] * Nx + AY[q] * Ny));
-            const float hs = h[q] - (h[q] - heq) * ie + AW9[q] * Q * A.inv_tau0;
-            Bb -= Pb * hold;
-            ia2b += Pb * hs;
-            const float hsb = Pb * ia2;
-            ieb += hsb * (heq - h[q]);
-            const float heqb = hsb * ie;
-            Qb += hsb * AW9[q] * A.inv_tau0;
-            phb += AW9[q] * heqb;
-            Nxb -= 3.f * AW9[q] * heqb * AX[q];
-            Nyb -= 3.f * AW9[q] * heqb * AY[q];
+            const float Bu = s_B[own - AY[q] * ALX - AX[q]];
+            gst<float>(lout + (5 + q) * pb, io, lh[q] * Ah - Bu * lo[q] + phb);
         }
-        phb += Qb * (1.f - 3.f * phi * phi - 4.f * A.lam * U * phi * om);
-        float Ub = Qb * A.lam * om * om;
-        ia2b += Bb;
-        const float a2b = -ia2 * ia2 * ia2b + 3.f * A.Dphi * (-ie * ie * ieb);
-        float ab = 2.f * a * a2b;
-        float Gxb = 0.f, Gyb = 0.f;
-        if (on) {
-            const float cb = gy * Nxb - gx * Nyb;  // N = c (gy, -gx)
-            Gxb += -c * Nyb;
-            Gyb += c * Nxb;
-            ab += A.coefN * A.eps * Sn * cb;
-            const float Sb = A.coefN * A.eps * a * cb;
-            deps = (double)(Cn * ab) + (double)(A.coefN * a * Sn * cb);
-            const float Cb = A.eps * ab;
-            const float m = (float)A.n_fold;
-            Gxb += (Cb * m * Sn * gy - Sb * m * Cn * gy) * iG2;
-            Gyb += (-Cb * m * Sn * gx + Sb * m * Cn * gx) * iG2;
-        }
-
-        // ---- reverse of the vapour collision and push
-        const float qd = 0.5f * (1.f - phi);
-        const bool inside = qd > 0.f && qd < 1.f;
-        const float itg = __builtin_amdgcn_rcpf(0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
-        float itgb = 0.f, srcb = 0.f, gsb[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            gsb[q] = lg[q];
-            itgb -= gsb[q] * (g[q] - AW5[q] * U);
-            Ub += AW5[q] * gsb[q] * itg;
-            srcb -= AW5[q] * gsb[q];
-        }
-        phb += A.half_Lsat * srcb;
-        if (inside) phb += -0.5f * A.tauv_m_half * (-itg * itg * itgb);
-        phb += lpp;  // phi_prev(t + 1) = phi(t)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) gst<float>(lout + q * pb, io, gsb[q] * (1.f - itg) + Ub);
-        gst<float>(lout + 14 * pb, io, -A.half_Lsat * srcb);
-        gst<float>(mid + 0 * pb, io, ia2 * (1.f - ie));
-        gst<float>(mid + 1 * pb, io, B);
-        gst<float>(mid + 2 * pb, io, Gxb);
-        gst<float>(mid + 3 * pb, io, Gyb);
-        gst<float>(mid + 4 * pb, io, phb);
     }
+
     // fixed-order workgroup reduction of the eps contribution
     const double w = wave_sum_d(deps);
     if (tid % 64 == 0) s_red[tid / 64] = w;
@@ -230,64 +299,6 @@ __global__ void __launch_bounds__(ANT) k_adj_a(AdjDesc A) {
         double t = 0.0;
         for (int k = 0; k < ANT / 64; ++k) t += s_red[k];
         A.epart[blockIdx.x] += t;
-    }
-}
-
-__global__ void __launch_bounds__(ANT) k_adj_b(AdjDesc A) {
-    // B, Gbar_x, Gbar_y of the tile and its ring in LDS (gathered at x - c_q and x - c_k)
-    __shared__ float s_B[ALN], s_Gx[ALN], s_Gy[ALN];
-    const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
-    const int ntx = (A.nx + ATX - 1) / ATX;
-    const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
-    const int x = x0 + tx, y = y0 + ty;
-    const bool active = x < A.nx && y < A.ny;
-    const int own = (ty + 1) * ALX + tx + 1;
-    const uint64_t pb = (uint64_t)A.plane * 4;
-    const GMEM char* lin = (const GMEM char*)A.lin;
-    GMEM char* lout = (GMEM char*)A.lout;
-    const GMEM char* mid = (const GMEM char*)A.mid;
-    {
-        const uint32_t oo = slot_off(A, x0, y0, own);
-        s_B[own] = gld<float>(mid + 1 * pb, oo);
-        s_Gx[own] = gld<float>(mid + 2 * pb, oo);
-        s_Gy[own] = gld<float>(mid + 3 * pb, oo);
-    }
-    if (tid < ARING) {
-        const int r = ring_slot(tid);
-        const uint32_t ro = slot_off(A, x0, y0, r);
-        s_B[r] = gld<float>(mid + 1 * pb, ro);
-        s_Gx[r] = gld<float>(mid + 2 * pb, ro);
-        s_Gy[r] = gld<float>(mid + 3 * pb, ro);
-    }
-    // the cell's own global loads are issued before the barrier too
-    const uint32_t xp = cell_xpart(x), yp = cell_ypart(A.nbx, y);
-    const uint32_t io = (xp + yp) * 4u;
-    const int yN = wrapn(y + 1, A.ny), yS = wrapn(y - 1, A.ny), xE = wrapn(x + 1, A.nx), xW = wrapn(x - 1, A.nx);
-    const uint32_t xpE = cell_xpart(xE), xpW = cell_xpart(xW);
-    const uint32_t ypN = cell_ypart(A.nbx, yN), ypS = cell_ypart(A.nbx, yS);
-    float phb = 0.f, Ah = 0.f, ld[9], lo[9];
-    if (active) {
-        phb = gld<float>(mid + 4 * pb, io);
-        Ah = gld<float>(mid + 0 * pb, io);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const uint32_t dO = ((AX[q] > 0 ? xpE : (AX[q] < 0 ? xpW : xp)) + (AY[q] > 0 ? ypN : (AY[q] < 0 ? ypS : yp))) * 4u;
-            ld[q] = gld<float>(lin + (5 + q) * pb, dO);  // lambda_h,q(x + c_q, t + 1)
-            lo[q] = gld<float>(lin + (5 + q) * pb, io);  // lambda_h,q(x, t + 1)
-        }
-    }
-    __syncthreads();
-    if (!active) return;
-#pragma unroll
-    for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
-        const int j = own - AY[k] * ALX - AX[k];
-        const float w = (k < 5) ? (1.f / 3.f) : (1.f / 12.f);
-        phb += w * (AX[k] * s_Gx[j] + AY[k] * s_Gy[j]);
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const float Bu = s_B[own - AY[q] * ALX - AX[q]];
-        gst<float>(lout + (5 + q) * pb, io, ld[q] * Ah - Bu * lo[q] + phb);
     }
 }
 
@@ -345,10 +356,7 @@ hipError_t launch_adj_seed(const AdjDesc& A, const float* dphi, hipStream_t s) {
 }
 
 hipError_t launch_adj_step(const AdjDesc& A, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_a, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_adj_b, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
+    hipLaunchKernelGGL(k_adj, dim3(adj_blocks(A)), dim3(ANT), 0, s, A);
     return hipGetLastError();
 }
 

@@ -359,7 +359,7 @@ struct snowlb_ctx {
         int64_t slot_bytes = 0, nslots = 0;
         int n = 0, stride = 0, nck = 0;
         bool have_forward = false;
-        float* buf = nullptr;  // lambda[0], lambda[1] (15 planes each), intermediates (5 planes)
+        float* buf = nullptr;  // lambda[0], lambda[1] (15 planes each)
         double* epart = nullptr;
         double* rows = nullptr;
         double* d_out = nullptr;
@@ -974,7 +974,7 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     A.tauv_m_half = c->dom.tauv_m_half;
     const int nblk = adj_blocks(A);
     if (!c->adj.buf) {
-        HIPCHK(c, hipMalloc(&c->adj.buf, (size_t)(35 * pb)));
+        HIPCHK(c, hipMalloc(&c->adj.buf, (size_t)(30 * pb)));
         HIPCHK(c, hipMalloc(&c->adj.epart, (size_t)nblk * sizeof(double)));
         HIPCHK(c, hipMalloc(&c->adj.rows, (size_t)c->p.ny * sizeof(double)));
         HIPCHK(c, hipMalloc(&c->adj.d_out, 2 * sizeof(double)));
@@ -998,7 +998,6 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
         c->adj.nsegdoms = (int)h.size();
     }
     float* lam[2] = {c->adj.buf, c->adj.buf + 15 * P};
-    A.mid = c->adj.buf + 30 * P;
     A.epart = c->adj.epart;
     HIPCHK(c, hipMemsetAsync(c->adj.epart, 0, (size_t)nblk * sizeof(double), s));
     A.lout = lam[0];

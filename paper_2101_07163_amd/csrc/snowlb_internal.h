@@ -115,7 +115,6 @@ struct AdjDesc {
     const float* st;     // state at t: g_0..4, h_0..8
     const float* lin;    // lambda(t+1): g_0..4, h_0..8, phi_prev
     float* lout;         // lambda(t)
-    float* mid;          // A_h, B, Gbar_x, Gbar_y, phibar
     double* epart;       // per-workgroup dL/deps partials, accumulated over the reverse sweep
     double grad_eps2;
     float eps, Dphi, coefN, inv_tau0, lam, half_Lsat, tauv_m_half, pad_;
