@@ -10,7 +10,7 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long CPU run (oracle closed forms at larger sizes)")
+    config.addinivalue_line("markers", "slow: long oracle run (closed forms at larger sizes, long GPU parity checkpoints)")
 
 
 def pytest_collection_modifyitems(config, items):

@@ -403,6 +403,30 @@ def test_ventilated_512_long_run(storage):
         assert errs["phi"] <= 1e-1
 
 
+@pytest.mark.slow
+def test_c2_ventilated_1024_checkpoints():
+    """The 1024^2 ventilated workload (inlet u = 0.02, U_in = U0 = 0.6, seed R = 8 at (300, 512),
+    tau_f = 0.6, tau_vap = 0.8) in FP32 storage against the FP64 oracle at checkpoints 1000 and 5000
+    steps; the error of every field is printed at each checkpoint.  The phase field is held to 1e-4
+    at 1000 steps and, like the 512^2 ventilated run, to 2e-3 at 5000 steps (FP32 rounding integrates
+    into a density drift under the open inlet/outlet pair).  About 6e9 oracle updates."""
+    cfg = W.C2
+    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
+    sim = S.Sim(cfg).init()
+    done = 0
+    for n, bar in ((1000, 1e-4), (5000, 2e-3)):
+        o.step(n - done)
+        sim.step(n - done)
+        done = n
+        F = o.fields()
+        errs = {k: float(np.abs(sim.read(k).double().cpu().numpy() - F[k]).max())
+                for k in ("phi", "U", "rho", "ux", "uy")}
+        for k, v in errs.items():
+            report("1024^2 %dk %s" % (n // 1000, k), v)
+        assert errs["phi"] <= bar, (n, errs)
+        assert all(np.isfinite(v) for v in errs.values())
+
+
 _ORACLE_CACHE = {}
 
 
