@@ -45,7 +45,7 @@ struct StateHeader {
     int64_t pop_bytes, phip_bytes, refs_bytes;
     uint64_t pad[9];
 };
-constexpr uint64_t kMagic = 0x534e4f574c423033ull;  // "SNOWLB03": 64 x 4 blocked cell order
+constexpr uint64_t kMagic = 0x534e4f574c423034ull;  // "SNOWLB04": 64 x 4 blocked cells, FP32 f as f - w
 static_assert(sizeof(StateHeader) == 128, "header size");
 constexpr int64_t kHeaderBytes = 256;
 
@@ -436,7 +436,7 @@ void fill_dom(snowlb_ctx* c) {
     const double u = p.u_in;
     for (int q = 0; q < 9; ++q) {
         const double cu = kCX[q] * u;
-        d.f_in[q] = (float)(kW9[q] * p.rho0 * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * u * u));
+        d.df_in[q] = (float)(kW9[q] * (p.rho0 - 1.0 + p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * u * u)));
     }
     for (int q = 0; q < 5; ++q) d.g_in[q] = (float)(kW5[q] * p.U_in * (1.0 + 3.0 * kCX[q] * u));
 }

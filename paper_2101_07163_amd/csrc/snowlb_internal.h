@@ -73,7 +73,7 @@ struct DomDesc {
     float ref_f;        // 16-bit storage reference of f (rho0)
     float U_in;         // inlet supersaturation
     float u_in;         // inlet x-velocity
-    float f_in[9];      // inlet ghost populations f_eq(rho0, (u_in, 0))
+    float df_in[9];     // inlet ghost populations f_eq(rho0, (u_in, 0)) - w (flow deviations)
     float g_in[5];      // inlet ghost populations g_eq(U_in, (u_in, 0))
     float pad_[3];
 };

@@ -89,6 +89,32 @@ __device__ __forceinline__ float f_ref(float rho, float jx, float jy, int cx, in
     return __builtin_fmaf(3.f, (float)cx * jx + (float)cy * jy, rho);
 }
 
+// Flow populations are carried as deviations from the lattice weights, df_q = f_q - w_q, through the
+// step: the density deviation, the momentum and every equilibrium and collision term are then small
+// numbers, so FP32 rounding acts on O(u) quantities rather than on O(1) ones.  FP32 storage holds df
+// itself; 16-bit storage keeps its deviation from the local reference and converts at the edges.
+template <class S>
+__device__ __forceinline__ float f_dev_dec(typename S::T v, int q, float m) {
+    if constexpr (S::kLocalRef) return S::dec(v, W9[q], m) - W9[q];
+    else return v;
+}
+template <class S>
+__device__ __forceinline__ typename S::T f_dev_enc(float df, int q, float m) {
+    if constexpr (S::kLocalRef) return S::enc(df + W9[q], IW9[q], m);
+    else return df;
+}
+// the same populations as plain FP32 values f_q (read-out, diagnostics, population exchange)
+template <class S>
+__device__ __forceinline__ float f_abs_dec(typename S::T v, int q, float m) {
+    if constexpr (S::kLocalRef) return S::dec(v, W9[q], m);
+    else return W9[q] + v;
+}
+template <class S>
+__device__ __forceinline__ typename S::T f_abs_enc(float f, int q, float m) {
+    if constexpr (S::kLocalRef) return S::enc(f, IW9[q], m);
+    else return f - W9[q];
+}
+
 // reference planes: U, rho, jx, jy (the last three with flow only)
 enum { R_U = 0, R_RHO = 1, R_JX = 2, R_JY = 3 };
 
@@ -185,7 +211,7 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
         float r[4];
         ref_at<S>(d, par, x - CX[q], y - CY[q], r);
         if (q < 5) g[q] = S::dec(plane_ptr<S>(d, par, d.off_g + q)[i], W5[q], r[R_U]);
-        f[q] = flow ? S::dec(plane_ptr<S>(d, par, q)[i], W9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]))
+        f[q] = flow ? f_abs_dec<S>(plane_ptr<S>(d, par, q)[i], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]))
                     : 0.f;
     }
 }
@@ -363,7 +389,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         const int ls = own - CY[q] * LX - CX[q];
                         m = f_ref(s_ref[R_RHO][ls], s_ref[R_JX][ls], s_ref[R_JY][ls], CX[q], CY[q]);
                     }
-                    f[q] = S::dec(fraw[q], W9[q], m);
+                    f[q] = f_dev_dec<S>(fraw[q], q, m);  // f_q - w_q
                 }
             }
             const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
@@ -416,11 +442,14 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             // ones, so that the zeroth moments close exactly in real arithmetic and only unbiased
             // rounding is left.
 
-            // ---- flow: drag and projection, Guo forcing, 2nd-order equilibrium (Sec. 2.2.1)
+            // ---- flow: drag and projection, Guo forcing, 2nd-order equilibrium (Sec. 2.2.1), all in
+            // deviations from the weights: f holds f_q - w_q, drho = rho - 1, and
+            // f_eq,q - w_q = w_q (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u.u))
             float ux = 0.f, uy = 0.f, rho = 0.f, jx = 0.f, jy = 0.f;
             float fs[9];
             if (FLOW) {
-                rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                const float drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                rho = 1.f + drho;
                 jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
                 jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 const float pc = fminf(fmaxf(phi, -1.f), 1.f);
@@ -436,10 +465,10 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 for (int q = 1; q < 9; ++q) {
                     const float cu = CX[q] * ux + CY[q] * uy;
                     const float cF = CX[q] * Fx + CY[q] * Fy;
-                    feq[q] = W9[q] * rho * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+                    feq[q] = W9[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
                     Sg[q] = d.guo * W9[q] * (3.f * (cF - uF) + 9.f * cu * cF);
                 }
-                feq[0] = rho - sum8(feq);
+                feq[0] = drho - sum8(feq);
                 Sg[0] = -sum8(Sg);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
@@ -509,7 +538,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                     const uint32_t dO = ((CX[q] > 0 ? xpE : (CX[q] < 0 ? xpW : xp)) + ypd) * ES;
                     const float href = REF ? (float)s_phi[lq] : 0.f;  // h references its holder's phi(t)
                     gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][lq], IW9[q], href));
-                    if (FLOW) gst<T>(pout + (PF + q) * pb, dO, S::enc(fs[q], IW9[q], fm));
+                    if (FLOW) gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
                     if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
                 }
                 if (INOUT) {
@@ -519,7 +548,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         const int ld = own + CY[q] * LX;
                         const float href = REF ? (float)s_phi[ld] : 0.f;
                         gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][ld], IW9[q], href));
-                        gst<T>(pout + (PF + q) * pb, dO, S::enc(fs[q], IW9[q], fm));
+                        gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
                         if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
                     }
                     if (CX[q] > 0 && x == 0) {
@@ -532,7 +561,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                             gfm = f_ref(s_ref[R_RHO][lg], s_ref[R_JX][lg], s_ref[R_JY][lg], CX[q], CY[q]);
                         }
                         gst<T>(pout + (PH + q) * pb, co * ES, S::enc(-W9[q], IW9[q], REF ? phi : 0.f));
-                        gst<T>(pout + (PF + q) * pb, co * ES, S::enc(d.f_in[q], IW9[q], gfm));
+                        gst<T>(pout + (PF + q) * pb, co * ES, f_dev_enc<S>(d.df_in[q], q, gfm));
                         if (q < 5) gst<T>(pout + (PG + q) * pb, co * ES, S::enc(d.g_in[q], IW5[q], ggm));
                     }
                 }
@@ -696,14 +725,14 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
 #pragma unroll
     for (int q = 0; q < 9; ++q)
         plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(hq[q], IW9[q], S::kLocalRef ? phi0 : 0.f);
-    float fq[9], gq[5];
-    const float uu = ux * ux;
+    float dfq[9], gq[5];  // f_eq - w in deviation form
+    const float uu = ux * ux, drho0 = rho0 - 1.f;
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
         const float cu = CX[q] * ux;
-        fq[q] = W9[q] * rho0 * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * uu);
+        dfq[q] = W9[q] * (drho0 + rho0 * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
     }
-    fq[0] = rho0 - sum8(fq);
+    dfq[0] = drho0 - sum8(dfq);
 #pragma unroll
     for (int q = 1; q < 5; ++q) gq[q] = W5[q] * U * (1.f + 3.f * CX[q] * ux);
     gq[0] = U - ((gq[1] + gq[2]) + (gq[3] + gq[4]));
@@ -711,7 +740,7 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
     for (int q = 0; q < 9; ++q) {
         float r[4] = {0.f, 0.f, 0.f, 0.f};
         if (S::kLocalRef) init_ref_at<S>(d, a, x - CX[q], y - CY[q], r);
-        if (flow) plane_ptr_w<S>(d, par, q)[i] = S::enc(fq[q], IW9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
+        if (flow) plane_ptr_w<S>(d, par, q)[i] = f_dev_enc<S>(dfq[q], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
         if (q < 5) plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], r[R_U]);
     }
 }
@@ -825,7 +854,7 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
             float r[4] = {0.f, 0.f, 0.f, 0.f};
             if (S::kLocalRef && d.inout && x - CX[q] < 0) ref_at<S>(d, par, -1, y - CY[q], r);  // ghost constants
             if (set == 0)
-                plane_ptr_w<S>(d, par, q)[i] = S::enc(canon[q * n + c], IW9[q], f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
+                plane_ptr_w<S>(d, par, q)[i] = f_abs_enc<S>(canon[q * n + c], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
             else
                 plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], r[R_U]);
         }
