@@ -218,8 +218,14 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
 
 // ---------------------------------------------------------------------------------------------
 // the fused step
+// 16-bit storage: at its natural 138 VGPRs the kernel runs 3 waves per SIMD; capping it at 6 (80 VGPRs,
+// a few spilled values) measured 7 % faster on the 2048^2 ventilated workload (caps of 4 and 5 were
+// slower: where the compiler spills decides it).  FP32 storage keeps the compiler's choice.
+template <class S>
+constexpr int step_waves_per_eu() { return S::kLocalRef ? 6 : 1; }
+
 template <int TX, int TY, class S, bool FLOW, bool INOUT>
-__global__ void __launch_bounds__(TX * TY)
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<S>())))
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
