@@ -15,8 +15,9 @@
 //                                     - B(x - c_q) lambda_h,q(x)      [destination term of Eq. (d)]
 //                                     + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)   [phi = sum h]
 //     with B and Gbar of the neighbours taken from LDS.
-// Layout: every field is an FP32 plane in the cell order of the state, with the state's plane stride;
-// the state slot holds g_0..4 then h_0..8; an adjoint slot holds g_0..4, h_0..8, phi_prev.
+// Layout: the state slot holds g_0..4 then h_0..8 in the populations' cell order (14 planes side by
+// side per 64 x 4 block); lambda of g_0..4, h_0..8 uses the same order, lambda of phi_prev is a plane
+// of its own.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -76,12 +77,12 @@ struct Nb {
 };
 __device__ __forceinline__ Nb nb_of(const AdjDesc& A, int gx, int gy) {
     Nb n;
-    n.xp = cell_xpart(wrapn(gx, A.nx));
-    n.xE = cell_xpart(wrapn(gx + 1, A.nx));
-    n.xW = cell_xpart(wrapn(gx - 1, A.nx));
-    n.yp = cell_ypart(A.nbx, wrapn(gy, A.ny));
-    n.yN = cell_ypart(A.nbx, wrapn(gy + 1, A.ny));
-    n.yS = cell_ypart(A.nbx, wrapn(gy - 1, A.ny));
+    n.xp = cell_xpart(wrapn(gx, A.nx), kAdjPlanes);
+    n.xE = cell_xpart(wrapn(gx + 1, A.nx), kAdjPlanes);
+    n.xW = cell_xpart(wrapn(gx - 1, A.nx), kAdjPlanes);
+    n.yp = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy, A.ny));
+    n.yN = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy + 1, A.ny));
+    n.yS = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy - 1, A.ny));
     return n;
 }
 
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < A.nx && y < A.ny;
-    const uint64_t pb = (uint64_t)A.plane * 4;  // bytes between planes
+    const uint64_t pb = (uint64_t)kBlockCells * 4;  // bytes between the planes of a block
     const GMEM char* st = (const GMEM char*)A.st;
     const GMEM char* lin = (const GMEM char*)A.lin;
     GMEM char* lout = (GMEM char*)A.lout;
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     if (active) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, on.dest(q));
-        lpp = gld<float>(lin + 14 * pb, on.at());
+        lpp = gld<float>((const GMEM char*)A.lppin, (cell_xpart(x, 1) + cell_ypart(A.nbx, 1, y)) * 4u);
 #pragma unroll
         for (int q = 0; q < 9; ++q) lo[q] = gld<float>(lin + (5 + q) * pb, on.at());
     }
@@ -231,7 +232,8 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     // ... and h(t) with phi(t) = sum h (FP64, as in the forward step) on the tile and two rings
     for (int r = tid; r < L2N; r += ANT) {
         const int lx = r % L2X, ly = r / L2X;
-        const uint32_t o = (cell_xpart(wrapn(x0 + lx - 2, A.nx)) + cell_ypart(A.nbx, wrapn(y0 + ly - 2, A.ny))) * 4u;
+        const uint32_t o =
+            (cell_xpart(wrapn(x0 + lx - 2, A.nx), kAdjPlanes) + cell_ypart(A.nbx, kAdjPlanes, wrapn(y0 + ly - 2, A.ny))) * 4u;
         double p = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
             const uint32_t io = on.at();
 #pragma unroll
             for (int q = 0; q < 5; ++q) gst<float>(lout + q * pb, io, lgo[q]);
-            gst<float>(lout + 14 * pb, io, lppo);
+            gst<float>((GMEM char*)A.lppout, (cell_xpart(x, 1) + cell_ypart(A.nbx, 1, y)) * 4u, lppo);
         } else {
             deps = 0.0;
         }
@@ -306,13 +308,13 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
 __global__ void __launch_bounds__(256) k_adj_seed(AdjDesc A, const float* __restrict__ dphi) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
     if (x >= A.nx || y >= A.ny) return;
-    const int64_t P = A.plane, i = cell_index(A.nbx, x, y);
+    const int64_t P = kBlockCells, i = cell_index(A.nbx, kAdjPlanes, x, y);
     const float v = dphi[(int64_t)y * A.nx + x];
 #pragma unroll
     for (int q = 0; q < 9; ++q) A.lout[(5 + q) * P + i] = v;
 #pragma unroll
     for (int q = 0; q < 5; ++q) A.lout[q * P + i] = 0.f;
-    A.lout[14 * P + i] = 0.f;
+    A.lppout[cell_index(A.nbx, 1, x, y)] = 0.f;
 }
 
 // dL/dU_init(x) = sum_q w_q lambda_g,q(x, 0) (the initial g_q = w_q U_init); per-row FP64 sums
@@ -321,10 +323,10 @@ __global__ void __launch_bounds__(256) k_adj_uinit(AdjDesc A, float* __restrict_
     const int y = blockIdx.x, tid = threadIdx.x;
     double acc = 0.0;
     for (int x = tid; x < A.nx; x += 256) {
-        const int64_t i = cell_index(A.nbx, x, y);
+        const int64_t i = cell_index(A.nbx, kAdjPlanes, x, y);
         float v = 0.f;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) v += AW5[q] * A.lin[q * A.plane + i];
+        for (int q = 0; q < 5; ++q) v += AW5[q] * A.lin[q * kBlockCells + i];
         dU[(int64_t)y * A.nx + x] = v;
         acc += v;
     }

@@ -45,7 +45,7 @@ struct StateHeader {
     int64_t pop_bytes, phip_bytes, refs_bytes;
     uint64_t pad[9];
 };
-constexpr uint64_t kMagic = 0x534e4f574c423034ull;  // "SNOWLB04": 64 x 4 blocked cells, FP32 f as f - w
+constexpr uint64_t kMagic = 0x534e4f574c423035ull;  // "SNOWLB05": interleaved 64 x 4 blocks, FP32 f as f - w
 static_assert(sizeof(StateHeader) == 128, "header size");
 constexpr int64_t kHeaderBytes = 256;
 
@@ -310,8 +310,10 @@ const char* validate_msg(const snowlb_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 2 || p->ny < 2) return "nx and ny must be >= 2";
     if (p->nx > 65536 || p->ny > 65536 ||
-        round_up(p->nx, kBlockX) * round_up(p->ny, kBlockY) > kMaxPlaneCells)
-        return "lattice too large (nx, ny <= 65536 and, padded to 64 x 4 blocks, at most 2^30 cells)";
+        round_up(p->nx, kBlockX) * round_up(p->ny, kBlockY) * (p->flow ? 23 : 14) *
+                (p->storage == SNOWLB_STORE_FP32 ? 4 : 2) > kMaxBufferBytes)
+        return "lattice too large (nx, ny <= 65536, and the populations of one copy, padded to 64 x 4 "
+               "blocks, within 4 GiB)";
     if (p->flow != 0 && p->flow != 1) return "flow must be 0 or 1";
     if (p->bc_x != SNOWLB_BC_PERIODIC && p->bc_x != SNOWLB_BC_INOUT) return "unknown bc_x";
     if (p->bc_x == SNOWLB_BC_INOUT && !p->flow) return "inflow/outflow needs flow = 1";
@@ -446,22 +448,20 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     const snowlb_params* p = &c->p;
     c->esize = p->storage == SNOWLB_STORE_FP32 ? 4 : 2;
     fill_dom(c);
-    // geometry: cells in blocks of 64 x 4 (the lattice padded up to whole blocks); planes padded to
-    // 64 KiB then staggered by 9 x 256 B
+    // geometry: cells in blocks of 64 x 4 (the lattice padded up to whole blocks), each block holding
+    // its planes side by side; every buffer padded to 64 KiB and then staggered by 9 x 256 B so that
+    // the buffers a tile touches do not start on the same HBM channel
     const int64_t stagger = env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
     const int64_t nbx = (p->nx + kBlockX - 1) / kBlockX;
     const int64_t cells = nbx * kBlockX * round_up(p->ny, kBlockY);
-    const int64_t plane_bytes = round_up(cells * c->esize, 65536) + stagger;
     c->dom.nbx = (int32_t)nbx;
-    c->dom.plane = plane_bytes / c->esize;
-    c->pop_bytes = round_up(plane_bytes * c->dom.npop, 65536);
+    c->dom.plane = kBlockCells;
+    c->dom.rplane = kBlockCells;
+    c->dom.nqr = p->flow ? 4 : 1;
+    c->pop_bytes = round_up(cells * c->dom.npop * c->esize, 65536) + stagger;
     c->phip_bytes = round_up(cells * 4, 65536) + stagger;
     c->local_ref = p->storage != SNOWLB_STORE_FP32;
-    int64_t rplane_bytes = 0;
-    if (c->local_ref) {
-        rplane_bytes = round_up(cells * c->esize, 65536) + stagger;
-        c->refs_bytes = round_up(rplane_bytes * (p->flow ? 4 : 1), 65536);
-    }
+    if (c->local_ref) c->refs_bytes = round_up(cells * c->dom.nqr * c->esize, 65536) + stagger;
     const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
     HIPCHK(c, hipMalloc(&c->mem, (size_t)total));
     // zero everything once: the 16-bit encodings reference phi_prev and the reference planes, which
@@ -474,7 +474,6 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     c->dom.phip[1] = (float*)(base + 2 * c->pop_bytes + c->phip_bytes);
     c->dom.refs[0] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes : nullptr;
     c->dom.refs[1] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes + c->refs_bytes : nullptr;
-    c->dom.rplane = rplane_bytes / c->esize;
     HIPCHK(c, hipMalloc(&c->d_dom, sizeof(DomDesc)));
     HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&c->d_partials, (size_t)diag_blocks(c->dom) * 8 * sizeof(double)));
@@ -847,6 +846,8 @@ static snowlb_status adj_check(snowlb_ctx* c) {
 }
 
 static char* adj_slot(snowlb_ctx* c, int64_t k) { return (char*)c->adj.slots + k * c->adj.slot_bytes; }
+// cells of the lattice padded to whole 64 x 4 blocks (the size of one plane of the cell order)
+static int64_t adj_cells(const snowlb_ctx* c) { return (int64_t)c->dom.nbx * kBlockX * round_up(c->p.ny, kBlockY); }
 
 snowlb_status snowlb_adj_forward(snowlb_ctx* c, int32_t n, int32_t stride, void* stream) {
     if (!c) return SNOWLB_EINVAL;
@@ -900,8 +901,8 @@ static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const la
     } key;
     std::memset(&key, 0, sizeof key);
     key.A = A;
-    key.A.st = key.A.lin = nullptr;
-    key.A.lout = nullptr;
+    key.A.st = key.A.lin = key.A.lppin = nullptr;
+    key.A.lout = key.A.lppout = nullptr;
     key.lam0 = lam[0];
     key.lam1 = lam[1];
     key.slots = c->adj.slots;
@@ -931,6 +932,8 @@ static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const la
         A.st = (const float*)adj_slot(c, c->adj.nck + i);
         A.lin = lam[cur];
         A.lout = lam[1 - cur];
+        A.lppin = lam[cur] + kAdjPlanes * adj_cells(c);
+        A.lppout = lam[1 - cur] + kAdjPlanes * adj_cells(c);
         le = launch_adj_step(A, cs);
         cur ^= 1;
     }
@@ -957,13 +960,13 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     if (!dphi || !dU || !deps || !dU0) return fail(c, SNOWLB_EINVAL, "NULL argument");
     if (!c->adj.have_forward) return fail(c, SNOWLB_ESTATE, "adjoint backward before adjoint forward");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t P = c->dom.plane, pb = P * 4;
+    // lambda buffers: the 14 planes of g and h in the populations' cell order, then phi_prev's plane
+    const int64_t cells = adj_cells(c);
     AdjDesc A{};
     A.nx = c->p.nx;
     A.ny = c->p.ny;
     A.nbx = c->dom.nbx;
     A.n_fold = c->p.n_fold;
-    A.plane = P;
     A.grad_eps2 = c->p.grad_eps2;
     A.eps = c->dom.eps;
     A.Dphi = c->dom.Dphi;
@@ -974,7 +977,7 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     A.tauv_m_half = c->dom.tauv_m_half;
     const int nblk = adj_blocks(A);
     if (!c->adj.buf) {
-        HIPCHK(c, hipMalloc(&c->adj.buf, (size_t)(30 * pb)));
+        HIPCHK(c, hipMalloc(&c->adj.buf, (size_t)(2 * (kAdjPlanes + 1) * cells * 4)));
         HIPCHK(c, hipMalloc(&c->adj.epart, (size_t)nblk * sizeof(double)));
         HIPCHK(c, hipMalloc(&c->adj.rows, (size_t)c->p.ny * sizeof(double)));
         HIPCHK(c, hipMalloc(&c->adj.d_out, 2 * sizeof(double)));
@@ -997,10 +1000,11 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
         HIPCHK(c, hipMemcpy(c->adj.d_segdoms, h.data(), h.size() * sizeof(DomDesc), hipMemcpyHostToDevice));
         c->adj.nsegdoms = (int)h.size();
     }
-    float* lam[2] = {c->adj.buf, c->adj.buf + 15 * P};
+    float* lam[2] = {c->adj.buf, c->adj.buf + (kAdjPlanes + 1) * cells};
     A.epart = c->adj.epart;
     HIPCHK(c, hipMemsetAsync(c->adj.epart, 0, (size_t)nblk * sizeof(double), s));
     A.lout = lam[0];
+    A.lppout = lam[0] + kAdjPlanes * cells;
     hipError_t e = launch_adj_seed(A, dphi, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint seed kernel");
     Driver& D = c->drv;

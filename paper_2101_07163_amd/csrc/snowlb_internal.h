@@ -1,12 +1,10 @@
 // snowlb_internal.h -- descriptors shared by the HIP kernels and the host runtime of libsnowlb.
 //
-// Device layout (per domain): structure-of-arrays population planes.  Inside a plane the cells are
-// ordered in blocks of 64 x 4 (cell_index below): blocks along x, block rows along y, each block
-// 4 rows of 64 cells.  Consecutive planes are `plane` elements apart (padded and staggered so that
-// the 23 streams of one tile do not start on the same HBM channel).  Plane order: f_0..f_8 (flow only), g_0..g_4,
-// h_0..h_8.  Two copies (pop[0], pop[1]) ping-pong between steps, and so do the FP32 plane phi_prev
-// and (16-bit storage only) the 16-bit reference planes U, rho, jx, jy that neighbours read to
-// decode the populations a cell emitted.
+// Device layout (per domain): the populations of one copy (f_0..f_8 with flow, g_0..g_4, h_0..h_8:
+// npop planes), phi_prev (one FP32 plane) and, for 16-bit storage, the 16-bit reference planes U, rho,
+// jx, jy (U only without flow) that neighbours read to decode the populations a cell emitted.  Every
+// such buffer stores the lattice in blocks of 64 x 4 cells with the block's planes side by side
+// (cell_index below).  Two copies of each (index par) ping-pong between steps.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -16,20 +14,24 @@ namespace snowlb {
 // address space of device global memory (lets the compiler emit global rather than flat accesses)
 #define GMEM __attribute__((address_space(1)))
 
-// Position of cell (x, y) inside a plane whose rows hold nbx blocks of 64 x 4 cells.  A workgroup
-// tile of 64 x 4 cells is then one contiguous 256-element run per plane, so the workgroups resident
-// at one time sweep a dense address range.  The index is separable into an x part and a y part.
-// Valid for 0 <= x < 64 nbx and 0 <= y with 64 nbx * round_up(y + 1, 4) <= 2^30 (the plane limit).
-constexpr int kBlockX = 64, kBlockY = 4;
-constexpr int64_t kMaxPlaneCells = int64_t(1) << 30;  // keeps every in-plane byte offset below 2^32
-__host__ __device__ __forceinline__ uint32_t cell_xpart(int x) {
-    return ((uint32_t)(x >> 6) << 8) + (uint32_t)(x & 63);
+// Cell order of a buffer of nq planes: blocks of 64 x 4 cells, blocks along x (nbx per block row) and
+// block rows along y; inside a block its nq planes follow each other as runs of 256 elements, each
+// run four rows of 64 cells.  Element (q, x, y) sits at
+//     ((y / 4) nbx + x / 64) nq 256  +  256 q  +  64 (y % 4)  +  x % 64,
+// so a 64 x 4 workgroup tile reads and writes one contiguous run of nq * 256 elements and the
+// workgroups resident at one time sweep a dense address range.  The index is separable (an x part
+// plus a y part), so the nine push destinations cost one add each.  The host keeps every byte offset
+// inside one buffer below 2^32.
+constexpr int kBlockX = 64, kBlockY = 4, kBlockCells = kBlockX * kBlockY;
+constexpr int64_t kMaxBufferBytes = int64_t(1) << 32;  // every in-buffer byte offset fits 32 bits
+__host__ __device__ __forceinline__ uint32_t cell_xpart(int x, int nq) {
+    return (uint32_t)(x >> 6) * ((uint32_t)nq << 8) + (uint32_t)(x & 63);
 }
-__host__ __device__ __forceinline__ uint32_t cell_ypart(int nbx, int y) {
-    return (uint32_t)(y >> 2) * ((uint32_t)nbx << 8) + ((uint32_t)(y & 3) << 6);
+__host__ __device__ __forceinline__ uint32_t cell_ypart(int nbx, int nq, int y) {
+    return (uint32_t)(y >> 2) * (((uint32_t)nbx * (uint32_t)nq) << 8) + ((uint32_t)(y & 3) << 6);
 }
-__host__ __device__ __forceinline__ int64_t cell_index(int nbx, int x, int y) {
-    return (int64_t)cell_ypart(nbx, y) + cell_xpart(x);
+__host__ __device__ __forceinline__ int64_t cell_index(int nbx, int nq, int x, int y) {
+    return (int64_t)cell_ypart(nbx, nq, y) + cell_xpart(x, nq);
 }
 
 // Global accesses of the hot kernels: a base that is uniform over the workgroup plus a 32-bit
@@ -50,15 +52,16 @@ __device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
 struct DomDesc {
     int32_t nx, ny, nbx, npop;    // nbx: 64 x 4 blocks per block row; npop: planes per copy (23 with
                                   // flow, 14 without)
-    int64_t plane;                // elements between consecutive planes
+    int64_t plane;                // elements between consecutive planes of a block (kBlockCells)
     void* pop[2];                 // the two population copies
-    float* phip[2];               // phi(t-1), FP32, same cell order
+    float* phip[2];               // phi(t-1), FP32, one plane (nq = 1)
     void* refs[2];                // 16-bit storage only: reference planes U, rho, jx, jy (else null)
-    int64_t rplane;               // elements between consecutive reference planes
+    int64_t rplane;               // elements between consecutive reference planes (kBlockCells)
     double grad_eps2;             // |grad phi|^2 (FP64) at or below which a = 1 and N = 0
     int32_t off_g, off_h;         // plane index of g_0 and h_0
     int32_t n_fold, storage;
-    int32_t inout, pad0;          // x closure: 1 = inlet/outlet
+    int32_t inout;                // x closure: 1 = inlet/outlet
+    int32_t nqr;                  // reference planes per buffer (4 with flow, 1 without)
     // physics in FP32 (lattice units)
     float eps;          // anisotropy strength
     float Dphi;         // W0^2 / tau0
@@ -111,14 +114,16 @@ hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s)
 // ---- discrete adjoint (snowlb_adjoint.hip): no flow, periodic, FP32 storage
 struct AdjDesc {
     int32_t nx, ny, nbx, n_fold;
-    int64_t plane;       // elements between planes of every slot below
-    const float* st;     // state at t: g_0..4, h_0..8
-    const float* lin;    // lambda(t+1): g_0..4, h_0..8, phi_prev
-    float* lout;         // lambda(t)
+    const float* st;     // state at t: g_0..4, h_0..8 (14 planes, the populations' cell order)
+    const float* lin;    // lambda(t+1) of g_0..4, h_0..8 (same order)
+    float* lout;         // lambda(t) of g_0..4, h_0..8
+    const float* lppin;  // lambda(t+1) of phi_prev (one plane)
+    float* lppout;       // lambda(t) of phi_prev
     double* epart;       // per-workgroup dL/deps partials, accumulated over the reverse sweep
     double grad_eps2;
     float eps, Dphi, coefN, inv_tau0, lam, half_Lsat, tauv_m_half, pad_;
 };
+constexpr int kAdjPlanes = 14;  // g_0..4, h_0..8 of the no-flow state
 int adj_blocks(const AdjDesc& A);
 hipError_t launch_adj_seed(const AdjDesc& A, const float* dphi, hipStream_t s);
 hipError_t launch_adj_step(const AdjDesc& A, hipStream_t s);

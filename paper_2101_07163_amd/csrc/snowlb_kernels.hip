@@ -147,21 +147,19 @@ __device__ __forceinline__ GMEM float* phip_ptr(const DomDesc& d, int par) {
 
 // Closure of the domain for a lattice position (gx, gy) that may lie outside it: y periodic; x
 // periodic, or (inlet/outlet) the inlet ghost left of x = 0 (returns false) and a copy of column
-// nx-1 right of it.  eo receives the in-plane element offset of the position it maps to.
+// nx-1 right of it.  (sx, sy) receives the position it maps to.
 template <bool INOUT>
-__device__ __forceinline__ bool map_off(const DomDesc& d, int gx, int gy, uint32_t& eo) {
-    const int sy = wrapi(gy, d.ny);
-    int sx;
+__device__ __forceinline__ bool map_pos(const DomDesc& d, int gx, int gy, int& sx, int& sy) {
+    sy = wrapi(gy, d.ny);
     if (INOUT) {
         if (gx < 0) {
-            eo = 0;
+            sx = 0;
             return false;
         }
         sx = gx < d.nx ? gx : d.nx - 1;
     } else {
         sx = wrapi(gx, d.nx);
     }
-    eo = cell_xpart(sx) + cell_ypart(d.nbx, sy);
     return true;
 }
 
@@ -186,7 +184,7 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
     } else {
         gx = wrapi(gx, d.nx);
     }
-    const int64_t i = cell_index(d.nbx, gx, sy);
+    const int64_t i = cell_index(d.nbx, d.nqr, gx, sy);
     const GMEM typename S::T* b = (const GMEM typename S::T*)(d.refs[par]);
     r[R_U] = S::from_ref(b[i]);
     if (d.npop == 23) {
@@ -202,8 +200,8 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
 template <class S>
 __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, int y, bool flow, float f[9],
                                             float g[5], float h[9]) {
-    const int64_t i = cell_index(d.nbx, x, y);
-    const float hr = S::kLocalRef ? phip_ptr(d, par)[i] : 0.f;
+    const int64_t i = cell_index(d.nbx, d.npop, x, y);
+    const float hr = S::kLocalRef ? phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)] : 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) h[q] = S::dec(plane_ptr<S>(d, par, d.off_h + q)[i], W9[q], hr);
 #pragma unroll
@@ -234,6 +232,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     constexpr int LX = TX + 2, LY = TY + 2, LN = LX * LY;
     constexpr int RING = 2 * LX + 2 * TY;
     constexpr int PF = 0, PG = FLOW ? 9 : 0, PH = PG + 5;  // first plane of f, g and h in a copy
+    constexpr int NP = FLOW ? 23 : 14;                     // population planes per copy (d.npop)
     constexpr uint32_t ES = sizeof(T);
     __shared__ double s_phi[LN];
     __shared__ float s_h[9][LN];
@@ -262,8 +261,8 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         const TileDesc td = tiles[t];
         const DomDesc& d = doms[td.dom];
         // uniform bases: population copies, phi_prev, reference planes
-        const uint64_t pb = (uint64_t)d.plane * ES;   // bytes between population planes
-        const uint64_t rb = (uint64_t)d.rplane * ES;  // bytes between reference planes
+        const uint64_t pb = (uint64_t)kBlockCells * ES;  // bytes between the planes of a block
+        const uint64_t rb = (uint64_t)kBlockCells * ES;
         const GMEM char* pin = (const GMEM char*)d.pop[par];
         GMEM char* pout = (GMEM char*)d.pop[npar];
         const GMEM char* phin = (const GMEM char*)d.phip[par];
@@ -273,8 +272,20 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
         const int x = td.x0 + tx, y = td.y0 + ty;
         const bool active = (x < d.nx) && (y < d.ny);
-        const uint32_t xp = cell_xpart(x), yp = cell_ypart(d.nbx, y);
-        const uint32_t co = xp + yp;  // element offset of this lane's cell (active lanes)
+        // element offsets of a position in the population buffer (p), the phi_prev plane (f) and the
+        // reference buffer (r)
+        struct Off {
+            uint32_t p, f, r;
+        };
+        auto offs = [&](int sx, int sy) {
+            Off o;
+            o.p = cell_xpart(sx, NP) + cell_ypart(d.nbx, NP, sy);
+            o.f = cell_xpart(sx, 1) + cell_ypart(d.nbx, 1, sy);
+            o.r = REF ? cell_xpart(sx, NR) + cell_ypart(d.nbx, NR, sy) : 0u;
+            return o;
+        };
+        const uint32_t xp = cell_xpart(x, NP), yp = cell_ypart(d.nbx, NP, y);
+        const uint32_t co = xp + yp;  // population offset of this lane's cell (active lanes)
 
         // ---- issue every global load of this tile first (own position and the first pass over the
         // halo ring, with the 16-bit references that decode them), so that they are all in flight
@@ -283,15 +294,16 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         T graw[5], fraw[9], hraw[9], rraw[9];
         T oref[NR], rref[NR];
         float ophi = 0.f, rphi = 0.f;  // phi_prev of the staged positions
-        uint32_t oo;
-        const bool oreal = map_off<INOUT>(d, x, y, oo);  // oo == co for active lanes
+        int osx, osy;
+        const bool oreal = map_pos<INOUT>(d, x, y, osx, osy);  // (x, y) itself for active lanes
+        const Off oo = offs(osx, osy);
         if (oreal) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) hraw[q] = gld<T>(pin + (PH + q) * pb, oo * ES);
-            ophi = gld<float>(phin, oo * 4);
+            for (int q = 0; q < 9; ++q) hraw[q] = gld<T>(pin + (PH + q) * pb, oo.p * ES);
+            ophi = gld<float>(phin, oo.f * 4);
             if (REF) {
 #pragma unroll
-                for (int k = 0; k < NR; ++k) oref[k] = gld<T>(rin + k * rb, oo * ES);
+                for (int k = 0; k < NR; ++k) oref[k] = gld<T>(rin + k * rb, oo.r * ES);
             }
         }
         if (active) {
@@ -303,19 +315,20 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             }
         }
         int rlx = 0, rly = 0;
-        uint32_t ro = 0;
         bool rreal = false;
         const bool has_ring = tid < RING;
         if (has_ring) {
             ring_pos(tid, rlx, rly);
-            rreal = map_off<INOUT>(d, td.x0 + rlx - 1, td.y0 + rly - 1, ro);
+            int sx, sy;
+            rreal = map_pos<INOUT>(d, td.x0 + rlx - 1, td.y0 + rly - 1, sx, sy);
+            const Off ro = offs(sx, sy);
             if (rreal) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) rraw[q] = gld<T>(pin + (PH + q) * pb, ro * ES);
+                for (int q = 0; q < 9; ++q) rraw[q] = gld<T>(pin + (PH + q) * pb, ro.p * ES);
                 if (REF) {
-                    rphi = gld<float>(phin, ro * 4);
+                    rphi = gld<float>(phin, ro.f * 4);
 #pragma unroll
-                    for (int k = 0; k < NR; ++k) rref[k] = gld<T>(rin + k * rb, ro * ES);
+                    for (int k = 0; k < NR; ++k) rref[k] = gld<T>(rin + k * rb, ro.r * ES);
                 }
             }
         }
@@ -363,17 +376,18 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         for (int r = tid + NT; r < RING; r += NT) {
             int lx, ly;
             ring_pos(r, lx, ly);
-            uint32_t eo;
-            const bool real = map_off<INOUT>(d, td.x0 + lx - 1, td.y0 + ly - 1, eo);
+            int sx, sy;
+            const bool real = map_pos<INOUT>(d, td.x0 + lx - 1, td.y0 + ly - 1, sx, sy);
+            const Off eo = offs(sx, sy);
             T raw[9], refs[NR];
             float pr = 0.f;
             if (real) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) raw[q] = gld<T>(pin + (PH + q) * pb, eo * ES);
+                for (int q = 0; q < 9; ++q) raw[q] = gld<T>(pin + (PH + q) * pb, eo.p * ES);
                 if (REF) {
-                    pr = gld<float>(phin, eo * 4);
+                    pr = gld<float>(phin, eo.f * 4);
 #pragma unroll
-                    for (int k = 0; k < NR; ++k) refs[k] = gld<T>(rin + k * rb, eo * ES);
+                    for (int k = 0; k < NR; ++k) refs[k] = gld<T>(rin + k * rb, eo.r * ES);
                 }
             }
             float hr[9];
@@ -512,13 +526,13 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             float rU = 0.f, rR = 0.f, rJx = 0.f, rJy = 0.f;
             if (REF) {
                 const T tU = S::to_ref(U);
-                gst<T>(rout, co * ES, tU);
+                gst<T>(rout, oo.r * ES, tU);
                 rU = S::from_ref(tU);
                 if (FLOW) {
                     const T tR = S::to_ref(rho), tX = S::to_ref(jx), tY = S::to_ref(jy);
-                    gst<T>(rout + rb, co * ES, tR);
-                    gst<T>(rout + 2 * rb, co * ES, tX);
-                    gst<T>(rout + 3 * rb, co * ES, tY);
+                    gst<T>(rout + rb, oo.r * ES, tR);
+                    gst<T>(rout + 2 * rb, oo.r * ES, tX);
+                    gst<T>(rout + 3 * rb, oo.r * ES, tY);
                     rR = S::from_ref(tR);
                     rJx = S::from_ref(tX);
                     rJy = S::from_ref(tY);
@@ -530,8 +544,8 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             const int yS = (y > 0) ? y - 1 : d.ny - 1;
             const int xE = (x + 1 < d.nx) ? x + 1 : (INOUT ? -1 : 0);
             const int xW = (x > 0) ? x - 1 : (INOUT ? -1 : d.nx - 1);
-            const uint32_t xpE = cell_xpart(xE < 0 ? 0 : xE), xpW = cell_xpart(xW < 0 ? 0 : xW);
-            const uint32_t ypN = cell_ypart(d.nbx, yN), ypS = cell_ypart(d.nbx, yS);
+            const uint32_t xpE = cell_xpart(xE < 0 ? 0 : xE, NP), xpW = cell_xpart(xW < 0 ? 0 : xW, NP);
+            const uint32_t ypN = cell_ypart(d.nbx, NP, yN), ypS = cell_ypart(d.nbx, NP, yS);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
@@ -572,7 +586,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                     }
                 }
             }
-            gst<float>(phout, co * 4, phi);
+            gst<float>(phout, oo.f * 4, phi);
         }
         __syncthreads();  // LDS is reused by the next tile
     }
@@ -713,15 +727,16 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
     const float rho0 = d.ref_f;
     float phi0, ux, U;
     init_at(d, a, x, y, phi0, ux, U);
-    const int64_t i = cell_index(d.nbx, x, y);
-    phip_ptr(d, par)[i] = phi0;
+    const int64_t i = cell_index(d.nbx, d.npop, x, y);
+    phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)] = phi0;
     if (S::kLocalRef) {
         GMEM typename S::T* wb = (GMEM typename S::T*)(d.refs[par]);
-        wb[i] = S::to_ref(U);
+        const int64_t ir = cell_index(d.nbx, d.nqr, x, y);
+        wb[ir] = S::to_ref(U);
         if (flow) {
-            wb[d.rplane + i] = S::to_ref(rho0);
-            wb[2 * d.rplane + i] = S::to_ref(rho0 * ux);
-            wb[3 * d.rplane + i] = S::to_ref(0.f);
+            wb[d.rplane + ir] = S::to_ref(rho0);
+            wb[2 * d.rplane + ir] = S::to_ref(rho0 * ux);
+            wb[3 * d.rplane + ir] = S::to_ref(0.f);
         }
     }
     float hq[9];
@@ -829,7 +844,7 @@ __global__ void k_pop_get(DomDesc d, int par, int set, float* __restrict__ canon
     if (x >= d.nx || y >= d.ny) return;
     const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x;
     if (set == 3) {
-        canon[c] = phip_ptr(d, par)[cell_index(d.nbx, x, y)];
+        canon[c] = phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)];
         return;
     }
     float f[9], g[5], h[9];
@@ -848,12 +863,13 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx || y >= d.ny) return;
-    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = cell_index(d.nbx, x, y);
+    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = cell_index(d.nbx, d.npop, x, y);
+    const int64_t i1 = cell_index(d.nbx, 1, x, y), ir = cell_index(d.nbx, d.nqr, x, y);
     GMEM typename S::T* wb = S::kLocalRef ? (GMEM typename S::T*)(d.refs[par]) : nullptr;
     if (set == 0 || set == 1) {
         if (S::kLocalRef) {
-            if (set == 1) wb[i] = S::to_ref(0.f);
-            else for (int k = 1; k < 4; ++k) wb[k * d.rplane + i] = S::to_ref(0.f);
+            if (set == 1) wb[ir] = S::to_ref(0.f);
+            else for (int k = 1; k < 4; ++k) wb[k * d.rplane + ir] = S::to_ref(0.f);
         }
         const int nq = set == 0 ? 9 : 5;
         for (int q = 0; q < nq; ++q) {
@@ -865,18 +881,18 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
                 plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], r[R_U]);
         }
     } else if (set == 2) {
-        const float ref = S::kLocalRef ? phip_ptr(d, par)[i] : 0.f;
+        const float ref = S::kLocalRef ? phip_ptr(d, par)[i1] : 0.f;
         for (int q = 0; q < 9; ++q) plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(canon[q * n + c], IW9[q], ref);
     } else {
         const float pnew = canon[c];
         if (S::kLocalRef) {
-            const float pold = phip_ptr(d, par)[i];
+            const float pold = phip_ptr(d, par)[i1];
             for (int q = 0; q < 9; ++q) {
                 GMEM typename S::T* p = plane_ptr_w<S>(d, par, d.off_h + q) + i;
                 *p = S::enc(S::dec(*p, W9[q], pold), IW9[q], pnew);
             }
         }
-        phip_ptr(d, par)[i] = pnew;
+        phip_ptr(d, par)[i1] = pnew;
     }
 }
 
@@ -946,7 +962,7 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DomDesc d, int par, doubl
                 jy += CY[q] * (double)f[q];
             }
         }
-        const float pp = phip_ptr(d, par)[cell_index(d.nbx, x, y)];
+        const float pp = phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)];
         bad |= !isfinite(pp);
         acc[0] += rho; acc[1] += jx; acc[2] += jy; acc[3] += U; acc[4] += phi; acc[5] += pp;
         acc[6] += (phi > 0.0) ? 1.0 : 0.0;

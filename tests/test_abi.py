@@ -100,15 +100,29 @@ def test_batch_rejects_mixed_kernels_before_gpu():
 
 
 def test_lattice_size_limit():
-    """Every in-plane byte offset of the step kernel is 32-bit: a plane padded to whole 64 x 4 blocks
-    may hold at most 2^30 cells.  The limit is checked on the host, before any GPU call."""
+    """Every byte offset of the step kernel inside one buffer is 32-bit: the populations of one copy,
+    on the lattice padded to whole 64 x 4 blocks, must fit in 4 GiB (23 planes with flow, 14 without;
+    4 B per value in FP32, 2 B in 16-bit storage).  Checked on the host, before any GPU call."""
+    def padded(n, m):
+        return -(-n // m) * m
+
+    for flow in (0, 1):
+        for storage, esize in ((S.STORE_FP32, 4), (S.STORE_FP16, 2)):
+            per_cell = (23 if flow else 14) * esize
+            # the widest square lattice that fits, and one block row more
+            n = 64
+            while padded(n + 64, 64) * padded(n + 64, 4) * per_cell <= 1 << 32:
+                n += 64
+            p = S.snowlb_params_default()
+            p.flow, p.storage = flow, storage
+            p.nx, p.ny = n, n
+            assert S.snowlb_validate(p) == (0, ""), (flow, storage, n)
+            ny = n
+            while padded(n, 64) * padded(ny, 4) * per_cell <= 1 << 32:
+                ny += 4
+            p.ny = ny
+            st, msg = S.snowlb_validate(p)
+            assert st == S.EINVAL and "too large" in msg, (flow, storage, n, ny)
     p = S.snowlb_params_default()
-    p.nx, p.ny = 32768, 32768                 # exactly 2^30 cells
-    assert S.snowlb_validate(p) == (0, "")
-    p.ny = 32769                              # padded to 32772 rows: over the limit
-    st, msg = S.snowlb_validate(p)
-    assert st == S.EINVAL and "too large" in msg
-    p.nx, p.ny = 32705, 32768                 # padded to 32768 columns: still exactly 2^30
-    assert S.snowlb_validate(p) == (0, "")
     p.nx, p.ny = 65537, 8
     assert S.snowlb_validate(p)[0] == S.EINVAL
