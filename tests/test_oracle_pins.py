@@ -377,6 +377,40 @@ def test_solid_is_at_rest():
     assert np.abs(o.fields()["ux"]).max() == 0.0
 
 
+@pytest.mark.parametrize("phi0", [-1.0, -0.6, 0.0, 0.3, 0.9, 1.0])
+def test_drag_and_projection_in_a_uniform_mush(phi0):
+    """A uniform state of partial solid phi0 in a periodic box: streaming moves nothing, so one step
+    changes the momentum only through the collision, and the first moment of the Guo-forced BGK
+    update gives it in closed form (Sec. 2.2.1): j' = j - (j - rho u)/tau_f + (1 - 1/(2 tau_f)) F,
+    with the projected velocity u = s j / (rho + k/2), s = (1 - phi0)/2, and the drag F = -k u,
+    k = h nu (1 + phi0)^2 (1 - phi0) / (4 W0^2), nu = (tau_f - 1/2)/3.  phi0 = -1 (fluid) keeps the
+    momentum; phi0 = 1 (ice) relaxes it as (1 - 1/tau_f).  This pins the drag magnitude and the
+    half-force velocity under the projection."""
+    n, tau, h, W0 = 6, 0.7, 2.757, 1.3
+    p = oracle.Params(nx=n, ny=n, flow=1, tau_f=tau, h_drag=h, W0=W0)
+    o = oracle.Oracle(p)
+    rho, u0 = 1.02, (0.012, -0.007)
+    f = oracle.feq(rho, *u0)[:, None, None] * np.ones((9, n, n))
+    o.set_state(f=f, g=np.zeros((5, n, n)), h=_uniform_phase(n, n, phi0), phip=phi0 * np.ones((n, n)))
+    cells = n * n
+    d0 = o.diag()
+    j0 = np.array([d0["jx"], d0["jy"]]) / cells
+    o.step(1)
+    d1 = o.diag()
+    j1 = np.array([d1["jx"], d1["jy"]]) / cells
+    s = 0.5 * (1 - phi0)
+    nu = (tau - 0.5) / 3
+    k = h * nu * (1 + phi0) ** 2 * (1 - phi0) / (4 * W0 * W0)
+    u = s * j0 / (rho + 0.5 * k)
+    want = j0 - (j0 - rho * u) / tau + (1 - 0.5 / tau) * (-k * u)
+    assert np.allclose(j1, want, rtol=1e-12, atol=1e-16), (j1, want)
+    assert abs(d1["rho"] - d0["rho"]) < 1e-12 * cells
+    if phi0 == -1.0:
+        assert np.allclose(j1, j0, rtol=1e-13)
+    if phi0 == 1.0:
+        assert np.allclose(j1, j0 * (1 - 1 / tau), rtol=1e-13)
+
+
 def test_uniform_inflow_is_a_fixed_point():
     """Ventilated domain without a crystal: the uniform inflow state (rho0, u_in; U_in; phi = -1)
     is preserved by the inlet ghost and the zero-gradient outlet (Sec. 3.1.3, 3.2.2)."""
