@@ -20,6 +20,14 @@
  *   - Fields are ny x nx, row-major, x fastest.  Population sets exchanged with the caller are in the
  *     canonical layout [q][y][x] as FP32, whatever the internal storage.
  *   - A context is used from one host thread at a time.
+ *
+ * Environment (read once per use, all optional)
+ *   SNOWLB_TUNE_CACHE      file of the autotuner's cache (default $HOME/.cache/snowlb_tune.txt)
+ *   SNOWLB_TUNE_STEPS      steps per timing sample of the autotuner (default 20, even)
+ *   SNOWLB_BUFFER_STAGGER  bytes added after each 64 KiB-padded buffer of a lattice so that the
+ *                          buffers a tile touches start on different HBM channels (default 2304)
+ *   SNOWLB_GRAPH_STEPS     steps per captured graph of snowlb_step (default 32, even)
+ *   SNOWLB_NO_GRAPH        1: launch every step directly instead of replaying graphs
  */
 #ifndef SNOWLB_H
 #define SNOWLB_H

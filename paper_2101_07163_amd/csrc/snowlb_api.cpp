@@ -254,8 +254,11 @@ std::string tune_cache_path() {
     return std::string(h ? h : "/tmp") + "/.cache/snowlb_tune.txt";
 }
 
-// Cache lines: "<key> <tile> <grid_mode>" where key is "nx ny storage flow bc" for one lattice and
-// "batch <ndomains> <cells> storage flow bc" for a batch.  The last matching line wins.
+// Cache lines: "<key> <tile> <grid_mode>" where key is "<layout> nx ny storage flow bc" for one
+// lattice and "<layout> batch <ndomains> <cells> storage flow bc" for a batch; <layout> names the
+// memory layout the timings were taken on, so a library with another layout re-tunes.  The last
+// matching line wins.
+constexpr const char* kTuneLayout = "L5";
 bool tune_lookup(const std::string& key, int& tile, int& mode) {
     FILE* f = std::fopen(tune_cache_path().c_str(), "r");
     if (!f) return false;
@@ -293,7 +296,7 @@ void tune_store(const std::string& key, int tile, int mode) {
 
 std::string tune_key(const snowlb_params& p) {
     char b[128];
-    std::snprintf(b, sizeof b, "%d %d %d %d %d", p.nx, p.ny, p.storage, p.flow, p.bc_x);
+    std::snprintf(b, sizeof b, "%s %d %d %d %d %d", kTuneLayout, p.nx, p.ny, p.storage, p.flow, p.bc_x);
     return b;
 }
 
@@ -451,7 +454,7 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     // geometry: cells in blocks of 64 x 4 (the lattice padded up to whole blocks), each block holding
     // its planes side by side; every buffer padded to 64 KiB and then staggered by 9 x 256 B so that
     // the buffers a tile touches do not start on the same HBM channel
-    const int64_t stagger = env_int("SNOWLB_PLANE_STAGGER", 9 * 256);
+    const int64_t stagger = env_int("SNOWLB_BUFFER_STAGGER", 9 * 256);
     const int64_t nbx = (p->nx + kBlockX - 1) / kBlockX;
     const int64_t cells = nbx * kBlockX * round_up(p->ny, kBlockY);
     c->dom.nbx = (int32_t)nbx;
@@ -1116,7 +1119,7 @@ snowlb_status snowlb_batch_init(snowlb_batch* b, void* stream) {
 static std::string batch_key(const snowlb_batch* b) {
     const snowlb_params& p = b->doms[0]->p;
     char k[160];
-    std::snprintf(k, sizeof k, "batch %d %lld %d %d %d", (int)b->doms.size(), (long long)b->cells, p.storage,
+    std::snprintf(k, sizeof k, "%s batch %d %lld %d %d %d", kTuneLayout, (int)b->doms.size(), (long long)b->cells, p.storage,
                   p.flow, p.bc_x);
     return k;
 }

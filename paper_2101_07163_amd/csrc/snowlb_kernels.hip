@@ -9,9 +9,10 @@
 //
 // The step is bound by HBM bandwidth (about 2 flop per byte against a balance of about 20), so the
 // kernel is built around memory traffic: every population is read once and written once per step,
-// in coalesced structure-of-arrays rows.  The only neighbour data the step needs -- phi at the eight
-// neighbours (gradient) and h_q at x + c_q (the destination term of Eq. (d)) -- is staged in LDS
-// from a one-cell halo of the 9 h planes, so halo re-reads hit LDS/L2 instead of HBM.
+// and a 64 x 4 tile's populations are one contiguous run of memory (planes side by side per block,
+// see cell_index).  The only neighbour data the step needs -- phi at the eight neighbours
+// (gradient) and h_q at x + c_q (the destination term of Eq. (d)) -- is staged in LDS from a
+// one-cell halo of the 9 h planes, so halo re-reads hit LDS/L2 instead of HBM.
 //
 // Streaming is "push": Eq. (d) evaluates a_s^2 at the source node and needs the destination's own
 // pre-collision h_q(x + c_q, t), so each cell writes h'_q(x + c_q) = P_q(x) - B(x) h_q(x + c_q, t),

@@ -3,7 +3,8 @@
 Argument marshalling only: every step of the method runs in the HIP kernels of libsnowlb.  The
 functions ``snowlb_*`` below carry the names and arguments of the C ABI; ``Sim`` is a convenience
 object around one context that takes device memory and streams from PyTorch.  Importing this
-module does not touch the GPU; loading the library fails loudly if it has not been built.
+module does not touch the GPU; loading the library fails loudly if it has not been built.  The
+library is ``_lib/libsnowlb.so`` next to this file, or the file named by ``SNOWLB_LIB``.
 """
 from __future__ import annotations
 
