@@ -41,8 +41,15 @@ def bytes_per_update(flow: bool, storage: str) -> int:
 
 
 def kernel_source_sha() -> str:
-    p = os.path.join(ROOT, "paper_2101_07163_amd", "csrc", "snowlb_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """Hash of the step kernel's code (its source and the shared header it indexes memory with),
+    comments and blank space removed, so that only a change of code marks counters as stale."""
+    h = hashlib.sha256()
+    for name in ("snowlb_kernels.hip", "snowlb_internal.h"):
+        for line in open(os.path.join(ROOT, "paper_2101_07163_amd", "csrc", name)):
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 
 
 def load_traffic(workload: str, storage: str):
