@@ -61,7 +61,7 @@ struct StoreF32 {
 struct StoreF16 {
     using T = _Float16;
     static constexpr bool kLocalRef = true;
-    static __device__ __forceinline__ float dec(T v, float w, float ref) { return w * (ref + (float)v); }
+    static __device__ __forceinline__ float dec(T v, float w, float ref) { return __builtin_fmaf(w, (float)v, w * ref); }
     static __device__ __forceinline__ T enc(float p, float iw, float ref) {
         return (_Float16)(p * iw - ref);  // v_cvt_f16_f32: round to nearest even
     }
@@ -72,14 +72,11 @@ struct StoreBF16 {
     using T = uint16_t;
     static constexpr bool kLocalRef = true;
     static __device__ __forceinline__ float dec(T v, float w, float ref) {
-        return w * (ref + __uint_as_float((uint32_t)v << 16));
+        return __builtin_fmaf(w, __uint_as_float((uint32_t)v << 16), w * ref);
     }
     static __device__ __forceinline__ T enc(float p, float iw, float ref) { return to_ref(p * iw - ref); }
     static __device__ __forceinline__ T to_ref(float v) {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);                                     // nearest even
-        return (T)(u >> 16);
+        return __builtin_bit_cast(uint16_t, (__bf16)v);  // v_cvt_pk_bf16_f32: nearest even
     }
     static __device__ __forceinline__ float from_ref(T v) { return __uint_as_float((uint32_t)v << 16); }
 };
