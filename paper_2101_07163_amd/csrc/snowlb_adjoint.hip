@@ -32,7 +32,7 @@ __device__ constexpr float AW9[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9
                                      1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 __device__ constexpr float AW5[5] = {1.f / 3.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f};
 
-constexpr int ATX = 64, ATY = 4, ANT = ATX * ATY;
+constexpr int ATX = 64, ATY = 8, ANT = ATX * ATY;
 constexpr int ALX = ATX + 2, ALY = ATY + 2, ALN = ALX * ALY;
 
 // i mod n for any i (one add or subtract in the common case: neighbours and halos of wide lattices)
