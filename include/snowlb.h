@@ -71,10 +71,11 @@ typedef int32_t snowlb_status;
 #define SNOWLB_POP_PHIP 3 /* 1 plane: phi at the previous step          */
 
 typedef struct {
-    int32_t nx, ny;     /* lattice size: 2 <= nx, ny <= 65536, and the populations of one copy on
-                           the lattice padded to whole 64 x 4 blocks within 4 GiB (every byte
-                           offset inside a buffer fits 32 bits): at most 46.7M cells in FP32
-                           with flow, 76.7M without; 93.4M / 153M in 16-bit storage            */
+    int32_t nx, ny;     /* lattice size: 2 <= nx, ny <= 65536, and the populations of one copy
+                           (with their 16-bit references) on the lattice padded to whole 64 x 4
+                           blocks within 4 GiB (every byte offset inside a buffer fits 32 bits):
+                           at most 46.7M cells in FP32 with flow, 76.7M without; 79.5M / 143M in
+                           16-bit storage                                                     */
     int32_t flow;       /* 1: D2Q9 flow solver on; 0: u = 0 (no f populations stored)           */
     int32_t bc_x;       /* SNOWLB_BC_PERIODIC or SNOWLB_BC_INOUT (needs flow = 1)               */
     int32_t storage;    /* SNOWLB_STORE_*                                                       */

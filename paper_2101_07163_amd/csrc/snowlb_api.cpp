@@ -42,10 +42,10 @@ struct StateHeader {
     uint64_t magic;
     int32_t nx, ny, storage, flow;
     int64_t step;
-    int64_t pop_bytes, phip_bytes, refs_bytes;
-    uint64_t pad[9];
+    int64_t pop_bytes, phip_bytes;
+    uint64_t pad[10];
 };
-constexpr uint64_t kMagic = 0x534e4f574c423035ull;  // "SNOWLB05": interleaved 64 x 4 blocks, FP32 f as f - w
+constexpr uint64_t kMagic = 0x534e4f574c423036ull;  // "SNOWLB06": 64 x 4 blocks, planes side by side, f as f - w
 static_assert(sizeof(StateHeader) == 128, "header size");
 constexpr int64_t kHeaderBytes = 256;
 
@@ -313,10 +313,11 @@ const char* validate_msg(const snowlb_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 2 || p->ny < 2) return "nx and ny must be >= 2";
     if (p->nx > 65536 || p->ny > 65536 ||
-        round_up(p->nx, kBlockX) * round_up(p->ny, kBlockY) * (p->flow ? 23 : 14) *
-                (p->storage == SNOWLB_STORE_FP32 ? 4 : 2) > kMaxBufferBytes)
-        return "lattice too large (nx, ny <= 65536, and the populations of one copy, padded to 64 x 4 "
-               "blocks, within 4 GiB)";
+        round_up(p->nx, kBlockX) * round_up(p->ny, kBlockY) *
+                (p->storage == SNOWLB_STORE_FP32 ? (p->flow ? 23 : 14) * 4 : (p->flow ? 27 : 15) * 2) >
+            kMaxBufferBytes)
+        return "lattice too large (nx, ny <= 65536, and the populations of one copy with their 16-bit "
+               "references, padded to 64 x 4 blocks, within 4 GiB)";
     if (p->flow != 0 && p->flow != 1) return "flow must be 0 or 1";
     if (p->bc_x != SNOWLB_BC_PERIODIC && p->bc_x != SNOWLB_BC_INOUT) return "unknown bc_x";
     if (p->bc_x == SNOWLB_BC_INOUT && !p->flow) return "inflow/outflow needs flow = 1";
@@ -348,7 +349,7 @@ struct snowlb_ctx {
     DomDesc dom{};
     DomDesc* d_dom = nullptr;
     void* mem = nullptr;  // one allocation: pop[0], pop[1], phip[0], phip[1], refs[0], refs[1]
-    int64_t pop_bytes = 0, phip_bytes = 0, refs_bytes = 0;
+    int64_t pop_bytes = 0, phip_bytes = 0;  // per copy; 16-bit references live in the population buffer
     bool local_ref = false;  // 16-bit storage: reference planes exist
     double* d_partials = nullptr;
     double* d_out = nullptr;
@@ -460,12 +461,11 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     c->dom.nbx = (int32_t)nbx;
     c->dom.plane = kBlockCells;
     c->dom.rplane = kBlockCells;
-    c->dom.nqr = p->flow ? 4 : 1;
-    c->pop_bytes = round_up(cells * c->dom.npop * c->esize, 65536) + stagger;
-    c->phip_bytes = round_up(cells * 4, 65536) + stagger;
     c->local_ref = p->storage != SNOWLB_STORE_FP32;
-    if (c->local_ref) c->refs_bytes = round_up(cells * c->dom.nqr * c->esize, 65536) + stagger;
-    const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes + 2 * c->refs_bytes;
+    c->dom.nqb = c->dom.npop + (c->local_ref ? (p->flow ? 4 : 1) : 0);
+    c->pop_bytes = round_up(cells * c->dom.nqb * c->esize, 65536) + stagger;
+    c->phip_bytes = round_up(cells * 4, 65536) + stagger;
+    const int64_t total = 2 * c->pop_bytes + 2 * c->phip_bytes;
     HIPCHK(c, hipMalloc(&c->mem, (size_t)total));
     // zero everything once: the 16-bit encodings reference phi_prev and the reference planes, which
     // must be defined even before the caller writes them
@@ -475,8 +475,10 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     c->dom.pop[1] = base + c->pop_bytes;
     c->dom.phip[0] = (float*)(base + 2 * c->pop_bytes);
     c->dom.phip[1] = (float*)(base + 2 * c->pop_bytes + c->phip_bytes);
-    c->dom.refs[0] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes : nullptr;
-    c->dom.refs[1] = c->local_ref ? base + 2 * c->pop_bytes + 2 * c->phip_bytes + c->refs_bytes : nullptr;
+    // 16-bit references: the planes after the populations inside each block of a copy
+    const int64_t rofs = (int64_t)c->dom.npop * kBlockCells * c->esize;
+    c->dom.refs[0] = c->local_ref ? (char*)c->dom.pop[0] + rofs : nullptr;
+    c->dom.refs[1] = c->local_ref ? (char*)c->dom.pop[1] + rofs : nullptr;
     HIPCHK(c, hipMalloc(&c->d_dom, sizeof(DomDesc)));
     HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&c->d_partials, (size_t)diag_blocks(c->dom) * 8 * sizeof(double)));
@@ -559,15 +561,12 @@ snowlb_status ctx_save(snowlb_ctx* c, int par, int64_t step, void* buf, hipStrea
     h->step = step;
     h->pop_bytes = c->pop_bytes;
     h->phip_bytes = c->phip_bytes;
-    h->refs_bytes = c->refs_bytes;
+
     char* b = (char*)buf;
     HIPCHK(c, hipMemcpyAsync(b, h, sizeof *h, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes, c->dom.pop[par], c->pop_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes, c->dom.phip[par], c->phip_bytes,
                              hipMemcpyDeviceToDevice, s));
-    if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->dom.refs[par], c->refs_bytes,
-                                 hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
     return SNOWLB_OK;
 }
@@ -579,20 +578,16 @@ snowlb_status ctx_load(snowlb_ctx* c, const void* buf, int64_t* step, hipStream_
     HIPCHK(c, hipStreamSynchronize(s));
     const StateHeader* h = c->h_hdr;
     if (h->magic != kMagic || h->nx != c->p.nx || h->ny != c->p.ny || h->storage != c->p.storage ||
-        h->flow != c->p.flow || h->pop_bytes != c->pop_bytes || h->phip_bytes != c->phip_bytes ||
-        h->refs_bytes != c->refs_bytes)
+        h->flow != c->p.flow || h->pop_bytes != c->pop_bytes || h->phip_bytes != c->phip_bytes)
         return fail(c, SNOWLB_EINVAL, "state buffer does not match this context");
     HIPCHK(c, hipMemcpyAsync(c->dom.pop[0], b + kHeaderBytes, c->pop_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->dom.phip[0], b + kHeaderBytes + c->pop_bytes, c->phip_bytes,
                              hipMemcpyDeviceToDevice, s));
-    if (c->local_ref)
-        HIPCHK(c, hipMemcpyAsync(c->dom.refs[0], b + kHeaderBytes + c->pop_bytes + c->phip_bytes, c->refs_bytes,
-                                 hipMemcpyDeviceToDevice, s));
     *step = h->step;
     return SNOWLB_OK;
 }
 
-int64_t ctx_state_bytes(const snowlb_ctx* c) { return kHeaderBytes + c->pop_bytes + c->phip_bytes + c->refs_bytes; }
+int64_t ctx_state_bytes(const snowlb_ctx* c) { return kHeaderBytes + c->pop_bytes + c->phip_bytes; }
 
 }  // namespace
 

@@ -1,10 +1,11 @@
 // snowlb_internal.h -- descriptors shared by the HIP kernels and the host runtime of libsnowlb.
 //
-// Device layout (per domain): the populations of one copy (f_0..f_8 with flow, g_0..g_4, h_0..h_8:
-// npop planes), phi_prev (one FP32 plane) and, for 16-bit storage, the 16-bit reference planes U, rho,
-// jx, jy (U only without flow) that neighbours read to decode the populations a cell emitted.  Every
-// such buffer stores the lattice in blocks of 64 x 4 cells with the block's planes side by side
-// (cell_index below).  Two copies of each (index par) ping-pong between steps.
+// Device layout (per domain): one buffer per copy holds the populations (f_0..f_8 with flow, g_0..g_4,
+// h_0..h_8: npop planes) followed, for 16-bit storage, by the 16-bit reference planes U, rho, jx, jy
+// (U only without flow) that neighbours read to decode the populations a cell emitted -- nqb planes
+// in all; phi_prev (one FP32 plane) has a buffer of its own.  Both store the lattice in blocks of
+// 64 x 4 cells with the block's planes side by side (cell_index below).  Two copies of each (index
+// par) ping-pong between steps.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -55,13 +56,15 @@ struct DomDesc {
     int64_t plane;                // elements between consecutive planes of a block (kBlockCells)
     void* pop[2];                 // the two population copies
     float* phip[2];               // phi(t-1), FP32, one plane (nq = 1)
-    void* refs[2];                // 16-bit storage only: reference planes U, rho, jx, jy (else null)
+    void* refs[2];                // 16-bit storage only: the reference planes U, rho, jx, jy, which
+                                  // follow the populations in pop[par] (else null)
     int64_t rplane;               // elements between consecutive reference planes (kBlockCells)
     double grad_eps2;             // |grad phi|^2 (FP64) at or below which a = 1 and N = 0
     int32_t off_g, off_h;         // plane index of g_0 and h_0
     int32_t n_fold, storage;
     int32_t inout;                // x closure: 1 = inlet/outlet
-    int32_t nqr;                  // reference planes per buffer (4 with flow, 1 without)
+    int32_t nqb;                  // planes per block of a population buffer: npop, plus the
+                                  // reference planes (4 with flow, 1 without) in 16-bit storage
     // physics in FP32 (lattice units)
     float eps;          // anisotropy strength
     float Dphi;         // W0^2 / tau0

@@ -182,7 +182,7 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
     } else {
         gx = wrapi(gx, d.nx);
     }
-    const int64_t i = cell_index(d.nbx, d.nqr, gx, sy);
+    const int64_t i = cell_index(d.nbx, d.nqb, gx, sy);
     const GMEM typename S::T* b = (const GMEM typename S::T*)(d.refs[par]);
     r[R_U] = S::from_ref(b[i]);
     if (d.npop == 23) {
@@ -198,7 +198,7 @@ __device__ __forceinline__ void ref_at(const DomDesc& d, int par, int gx, int gy
 template <class S>
 __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, int y, bool flow, float f[9],
                                             float g[5], float h[9]) {
-    const int64_t i = cell_index(d.nbx, d.npop, x, y);
+    const int64_t i = cell_index(d.nbx, d.nqb, x, y);
     const float hr = S::kLocalRef ? phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)] : 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) h[q] = S::dec(plane_ptr<S>(d, par, d.off_h + q)[i], W9[q], hr);
@@ -230,7 +230,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     constexpr int LX = TX + 2, LY = TY + 2, LN = LX * LY;
     constexpr int RING = 2 * LX + 2 * TY;
     constexpr int PF = 0, PG = FLOW ? 9 : 0, PH = PG + 5;  // first plane of f, g and h in a copy
-    constexpr int NP = FLOW ? 23 : 14;                     // population planes per copy (d.npop)
+    constexpr int NP = (FLOW ? 23 : 14) + (REF ? NR : 0);  // planes per block of a copy (d.nqb)
     constexpr uint32_t ES = sizeof(T);
     __shared__ double s_phi[LN];
     __shared__ float s_h[9][LN];
@@ -270,8 +270,8 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
         const int x = td.x0 + tx, y = td.y0 + ty;
         const bool active = (x < d.nx) && (y < d.ny);
-        // element offsets of a position in the population buffer (p), the phi_prev plane (f) and the
-        // reference buffer (r)
+        // element offsets of a position in the population buffer (p; the 16-bit reference planes share
+        // its blocks, r = p) and in the phi_prev plane (f)
         struct Off {
             uint32_t p, f, r;
         };
@@ -279,7 +279,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             Off o;
             o.p = cell_xpart(sx, NP) + cell_ypart(d.nbx, NP, sy);
             o.f = cell_xpart(sx, 1) + cell_ypart(d.nbx, 1, sy);
-            o.r = REF ? cell_xpart(sx, NR) + cell_ypart(d.nbx, NR, sy) : 0u;
+            o.r = o.p;
             return o;
         };
         const uint32_t xp = cell_xpart(x, NP), yp = cell_ypart(d.nbx, NP, y);
@@ -725,11 +725,11 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
     const float rho0 = d.ref_f;
     float phi0, ux, U;
     init_at(d, a, x, y, phi0, ux, U);
-    const int64_t i = cell_index(d.nbx, d.npop, x, y);
+    const int64_t i = cell_index(d.nbx, d.nqb, x, y);
     phip_ptr(d, par)[cell_index(d.nbx, 1, x, y)] = phi0;
     if (S::kLocalRef) {
         GMEM typename S::T* wb = (GMEM typename S::T*)(d.refs[par]);
-        const int64_t ir = cell_index(d.nbx, d.nqr, x, y);
+        const int64_t ir = i;  // the reference planes share the populations' blocks
         wb[ir] = S::to_ref(U);
         if (flow) {
             wb[d.rplane + ir] = S::to_ref(rho0);
@@ -861,8 +861,8 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx || y >= d.ny) return;
-    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = cell_index(d.nbx, d.npop, x, y);
-    const int64_t i1 = cell_index(d.nbx, 1, x, y), ir = cell_index(d.nbx, d.nqr, x, y);
+    const int64_t n = (int64_t)d.nx * d.ny, c = (int64_t)y * d.nx + x, i = cell_index(d.nbx, d.nqb, x, y);
+    const int64_t i1 = cell_index(d.nbx, 1, x, y), ir = i;
     GMEM typename S::T* wb = S::kLocalRef ? (GMEM typename S::T*)(d.refs[par]) : nullptr;
     if (set == 0 || set == 1) {
         if (S::kLocalRef) {

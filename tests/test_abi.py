@@ -100,15 +100,16 @@ def test_batch_rejects_mixed_kernels_before_gpu():
 
 
 def test_lattice_size_limit():
-    """Every byte offset of the step kernel inside one buffer is 32-bit: the populations of one copy,
-    on the lattice padded to whole 64 x 4 blocks, must fit in 4 GiB (23 planes with flow, 14 without;
-    4 B per value in FP32, 2 B in 16-bit storage).  Checked on the host, before any GPU call."""
+    """Every byte offset of the step kernel inside one buffer is 32-bit: the populations of one copy
+    (with the 16-bit reference planes in 16-bit storage), on the lattice padded to whole 64 x 4
+    blocks, must fit in 4 GiB: 23 planes with flow and 14 without at 4 B in FP32; 27 and 15 planes at
+    2 B in 16-bit storage.  Checked on the host, before any GPU call."""
     def padded(n, m):
         return -(-n // m) * m
 
     for flow in (0, 1):
         for storage, esize in ((S.STORE_FP32, 4), (S.STORE_FP16, 2)):
-            per_cell = (23 if flow else 14) * esize
+            per_cell = (23 if flow else 14) * 4 if esize == 4 else (27 if flow else 15) * 2
             # the widest square lattice that fits, and one block row more
             n = 64
             while padded(n + 64, 64) * padded(n + 64, 4) * per_cell <= 1 << 32:
