@@ -143,6 +143,13 @@ __device__ __forceinline__ GMEM float* phip_ptr(const DomDesc& d, int par) {
     return (GMEM float*)(d.phip[par]);
 }
 
+// The y part of cell_index with a full-rate 24-bit multiply (v_mul_u32_u24): every lattice the host
+// accepts has fewer than 2^14 block rows and a block-row stride (64 nbx nq) below 2^24 elements, and its
+// offsets below 2^32.
+__device__ __forceinline__ uint32_t cell_ypart24(int nbx, int nq, int y) {
+    return __umul24((uint32_t)(y >> 2), ((uint32_t)nbx * (uint32_t)nq) << 8) + ((uint32_t)(y & 3) << 6);
+}
+
 // Closure of the domain for a lattice position (gx, gy) that may lie outside it: y periodic; x
 // periodic, or (inlet/outlet) the inlet ghost left of x = 0 (returns false) and a copy of column
 // nx-1 right of it.  (sx, sy) receives the position it maps to.
@@ -214,14 +221,8 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
 
 // ---------------------------------------------------------------------------------------------
 // the fused step
-// 16-bit storage: at its natural 138 VGPRs the kernel runs 3 waves per SIMD; capping it at 6 (80 VGPRs,
-// a few spilled values) measured 7 % faster on the 2048^2 ventilated workload (caps of 4 and 5 were
-// slower: where the compiler spills decides it).  FP32 storage keeps the compiler's choice.
-template <class S>
-constexpr int step_waves_per_eu() { return S::kLocalRef ? 6 : 1; }
-
 template <int TX, int TY, class S, bool FLOW, bool INOUT>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(step_waves_per_eu<S>())))
+__global__ void __launch_bounds__(TX * TY)
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
@@ -277,12 +278,12 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         };
         auto offs = [&](int sx, int sy) {
             Off o;
-            o.p = cell_xpart(sx, NP) + cell_ypart(d.nbx, NP, sy);
-            o.f = cell_xpart(sx, 1) + cell_ypart(d.nbx, 1, sy);
+            o.p = cell_xpart(sx, NP) + cell_ypart24(d.nbx, NP, sy);
+            o.f = cell_xpart(sx, 1) + cell_ypart24(d.nbx, 1, sy);
             o.r = o.p;
             return o;
         };
-        const uint32_t xp = cell_xpart(x, NP), yp = cell_ypart(d.nbx, NP, y);
+        const uint32_t xp = cell_xpart(x, NP), yp = cell_ypart24(d.nbx, NP, y);
         const uint32_t co = xp + yp;  // population offset of this lane's cell (active lanes)
 
         // ---- issue every global load of this tile first (own position and the first pass over the
@@ -543,7 +544,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             const int xE = (x + 1 < d.nx) ? x + 1 : (INOUT ? -1 : 0);
             const int xW = (x > 0) ? x - 1 : (INOUT ? -1 : d.nx - 1);
             const uint32_t xpE = cell_xpart(xE < 0 ? 0 : xE, NP), xpW = cell_xpart(xW < 0 ? 0 : xW, NP);
-            const uint32_t ypN = cell_ypart(d.nbx, NP, yN), ypS = cell_ypart(d.nbx, NP, yS);
+            const uint32_t ypN = cell_ypart24(d.nbx, NP, yN), ypS = cell_ypart24(d.nbx, NP, yS);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
                 const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
