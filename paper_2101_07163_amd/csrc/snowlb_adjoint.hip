@@ -109,7 +109,7 @@ __device__ __forceinline__ void pass_a(const AdjDesc& A, const double* s_phi, co
     const float gx = (float)gx64, gy = (float)gy64;
     float a = 1.f, Cn = 0.f, Sn = 0.f, c = 0.f, iG2 = 0.f;
     if (on) {
-        iG2 = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
+        iG2 = 1.f / (gx * gx + gy * gy);
         const float X = gx * gx * iG2, Y = gy * gy * iG2, XY = gx * gy * iG2;
         if (A.n_fold == 6) {
             Cn = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
@@ -122,8 +122,8 @@ __device__ __forceinline__ void pass_a(const AdjDesc& A, const double* s_phi, co
         c = A.coefN * A.eps * a * Sn;
     }
     const float Nx = c * gy, Ny = -c * gx;
-    const float a2 = a * a, ia2 = __builtin_amdgcn_rcpf(a2), B = ia2 - 1.f;
-    const float ie = __builtin_amdgcn_rcpf(3.f * A.Dphi * a2 + 0.5f);
+    const float a2 = a * a, ia2 = 1.f / a2, B = ia2 - 1.f;
+    const float ie = 1.f / (3.f * A.Dphi * a2 + 0.5f);
     const float om = 1.f - phi * phi;
     const float Q = phi - phi * phi * phi + A.lam * U * om * om;
 
@@ -170,7 +170,7 @@ __device__ __forceinline__ void pass_a(const AdjDesc& A, const double* s_phi, co
     // ---- reverse of the vapour collision and push
     const float qd = 0.5f * (1.f - phi);
     const bool inside = qd > 0.f && qd < 1.f;
-    const float itg = __builtin_amdgcn_rcpf(0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
+    const float itg = 1.f / (0.5f + A.tauv_m_half * fminf(fmaxf(qd, 0.f), 1.f));
     float itgb = 0.f, srcb = 0.f;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {

@@ -428,10 +428,9 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             // polynomials in the unit normal (theta-free, sign-free): with X = gx^2/|g|^2,
             // Y = gy^2/|g|^2, cos 6t = X^3 - 15 X^2 Y + 15 X Y^2 - Y^3,
             // sin 6t = (gx gy/|g|^2)(6 X^2 - 20 X Y + 6 Y^2), and d cos(nt)/dg = n sin(nt)(gy,-gx)/|g|^2.
-            // Reciprocals use the hardware v_rcp_f32 (1 ulp); every operand is a normal number here.
             float a = 1.f, Nx = 0.f, Ny = 0.f;
             if (has_normal) {
-                const float inv = __builtin_amdgcn_rcpf(gx * gx + gy * gy);
+                const float inv = 1.f / (gx * gx + gy * gy);
                 const float X = gx * gx * inv, Y = gy * gy * inv, XY = gx * gy * inv;
                 float Cn, Sn;
                 if (d.n_fold == 6) {
@@ -449,9 +448,9 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
             // ---- phase field, Eq. (d)/(e): relaxation eta = a^2 Dphi / cs^2 + 1/2, source Q / tau0
             const float a2 = a * a;
-            const float ia2 = __builtin_amdgcn_rcpf(a2);
+            const float ia2 = 1.f / a2;
             const float B = ia2 - 1.f;
-            const float ieta = __builtin_amdgcn_rcpf(3.f * d.Dphi * a2 + 0.5f);
+            const float ieta = 1.f / (3.f * d.Dphi * a2 + 0.5f);
             const float om = 1.f - phi * phi;
             const float srcQ = (phi - phi * phi * phi + d.lam * U * om * om) * d.inv_tau0;
 
@@ -473,7 +472,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 const float pc = fminf(fmaxf(phi, -1.f), 1.f);
                 const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
-                const float sc = 0.5f * (1.f - pc) * __builtin_amdgcn_rcpf(rho + 0.5f * k);
+                const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
                 ux = jx * sc;
                 uy = jy * sc;
                 const float Fx = -k * ux, Fy = -k * uy;
@@ -495,7 +494,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
             // ---- vapour (Sec. 2.2.2): tau_g = 1/2 + (tau_vap - 1/2) clamp((1 - phi)/2, 0, 1)
             const float sq = fminf(fmaxf(0.5f * (1.f - phi), 0.f), 1.f);
-            const float itg = __builtin_amdgcn_rcpf(0.5f + d.tauv_m_half * sq);
+            const float itg = 1.f / (0.5f + d.tauv_m_half * sq);
             const float srcg = d.half_Lsat * (phi - phip);
             float gs[5];
             {
