@@ -19,7 +19,9 @@
  *     asynchronously on it unless stated otherwise.
  *   - Fields are ny x nx, row-major, x fastest.  Population sets exchanged with the caller are in the
  *     canonical layout [q][y][x] as FP32, whatever the internal storage.
- *   - A context is used from one host thread at a time.
+ *   - A context is used from one host thread at a time; distinct contexts may be used concurrently.
+ *     The library keeps no global mutable state except the per-thread error string of context-free
+ *     calls and the autotuner's cache file (read and appended under file locks).
  *
  * Environment (read once per use, all optional)
  *   SNOWLB_TUNE_CACHE      file of the autotuner's cache (default $HOME/.cache/snowlb_tune.txt)

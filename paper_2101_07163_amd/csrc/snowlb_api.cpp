@@ -6,6 +6,7 @@
 // grid-mode autotuner and its cache, FP64 diagnostics, field read-out and checkpoints.  Every HIP
 // call is checked; errors are returned as status codes with a message.
 #include <hip/hip_runtime.h>
+#include <sys/file.h>
 #include <sys/stat.h>
 
 #include <algorithm>
@@ -259,9 +260,11 @@ std::string tune_cache_path() {
 // memory layout the timings were taken on, so a library with another layout re-tunes.  The last
 // matching line wins.
 constexpr const char* kTuneLayout = "L5";
+// The cache may be shared by several processes: readers take a shared lock, writers an exclusive one.
 bool tune_lookup(const std::string& key, int& tile, int& mode) {
     FILE* f = std::fopen(tune_cache_path().c_str(), "r");
     if (!f) return false;
+    (void)flock(fileno(f), LOCK_SH);
     char line[512];
     bool found = false;
     while (std::fgets(line, sizeof line, f)) {
@@ -280,6 +283,7 @@ bool tune_lookup(const std::string& key, int& tile, int& mode) {
             found = true;
         }
     }
+    (void)flock(fileno(f), LOCK_UN);
     std::fclose(f);
     return found;
 }
@@ -290,7 +294,10 @@ void tune_store(const std::string& key, int tile, int mode) {
     if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);  // best effort
     FILE* f = std::fopen(path.c_str(), "a");
     if (!f) return;
+    (void)flock(fileno(f), LOCK_EX);
     std::fprintf(f, "%s %d %d\n", key.c_str(), tile, mode);
+    std::fflush(f);
+    (void)flock(fileno(f), LOCK_UN);
     std::fclose(f);
 }
 
