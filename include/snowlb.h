@@ -139,6 +139,14 @@ int64_t snowlb_step_count(const snowlb_ctx* ctx);
 snowlb_status snowlb_read(snowlb_ctx* ctx, int32_t field, float* dst_dev, int64_t dst_elems,
                           void* stream);
 
+/* Debugging and tests: overwrite one macroscopic field of the current state from src_dev (float,
+ * src_elems >= nx*ny, caller-owned, x fastest).  SNOWLB_FIELD_PHI sets h_q = w_q phi and
+ * phi_prev = phi (the phase field at rest, without the anisotropic flux); SNOWLB_FIELD_U sets
+ * g_q = g_eq(U, u) with the velocity u the collisions currently see (0 without flow).  Other fields:
+ * SNOWLB_EINVAL.  Needs an initialised state (SNOWLB_ESTATE otherwise). */
+snowlb_status snowlb_write_field(snowlb_ctx* ctx, int32_t field, const float* src_dev, int64_t src_elems,
+                                 void* stream);
+
 /* Copy a population set (SNOWLB_POP_*) of the current state to / from caller memory in the canonical
  * FP32 layout [q][y][x] (elems >= Q*nx*ny).  Writing encodes into the context's storage format. */
 snowlb_status snowlb_read_populations(snowlb_ctx* ctx, int32_t set, float* dst_dev, int64_t elems,

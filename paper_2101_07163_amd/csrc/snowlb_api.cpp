@@ -769,6 +769,17 @@ snowlb_status snowlb_read_populations(snowlb_ctx* c, int32_t set, float* dst, in
     return SNOWLB_OK;
 }
 
+snowlb_status snowlb_write_field(snowlb_ctx* c, int32_t field, const float* src, int64_t elems, void* stream) {
+    if (!c) return SNOWLB_EINVAL;
+    if (field != SNOWLB_FIELD_PHI && field != SNOWLB_FIELD_U)
+        return fail(c, SNOWLB_EINVAL, "only SNOWLB_FIELD_PHI and SNOWLB_FIELD_U can be written");
+    if (!src || elems < (int64_t)c->p.nx * c->p.ny) return fail(c, SNOWLB_EINVAL, "src too small");
+    if (!c->inited) return fail(c, SNOWLB_ESTATE, "write_field before init");
+    hipError_t e = launch_write_field(c->dom, c->drv.par, field, src, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "field write kernel");
+    return SNOWLB_OK;
+}
+
 snowlb_status snowlb_write_populations(snowlb_ctx* c, int32_t set, const float* src, int64_t elems,
                                        void* stream) {
     if (!c) return SNOWLB_EINVAL;

@@ -105,6 +105,7 @@ int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout, int gr
 hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float seed_x,
                        float seed_y, float seed_r, float width, float u_in, hipStream_t s);
 hipError_t launch_read(const DomDesc& d, int par, int field, float* dst, hipStream_t s);
+hipError_t launch_write_field(const DomDesc& d, int par, int field, const float* src, hipStream_t s);
 hipError_t launch_pop_io(const DomDesc& d, int par, int set, int to_canonical, float* canon,
                          hipStream_t s);
 // FP64 diagnostics: partials (nblk x 8 doubles) then out[8]; returns the number of blocks used via

@@ -834,6 +834,74 @@ hipError_t launch_read(const DomDesc& d, int par, int field, float* dst, hipStre
 }
 
 // ---------------------------------------------------------------------------------------------
+// overwrite one macroscopic field (debugging and tests): PHI sets h_q = w_q phi with phi_prev = phi (the
+// phase field at rest, no anisotropic flux); U sets g_q = g_eq(U, u) with the velocity u the
+// collisions currently see (0 without flow).  16-bit storage encodes h against the new phi_prev and g
+// against a U reference reset to 0 (inlet-ghost sources keep the ghost constant), as a population
+// write does.  The U case reads only f, h and phi_prev, none of which it writes.
+template <class S>
+__global__ void k_write_field(DomDesc d, int par, int field, const float* __restrict__ src) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= d.nx || y >= d.ny) return;
+    const int64_t i = cell_index(d.nbx, d.nqb, x, y), i1 = cell_index(d.nbx, 1, x, y);
+    const float v = src[(int64_t)y * d.nx + x];
+    if (field == 0) {
+        phip_ptr(d, par)[i1] = v;
+        float hq[9];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) hq[q] = W9[q] * v;
+        hq[0] = v - sum8(hq);
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            plane_ptr_w<S>(d, par, d.off_h + q)[i] = S::enc(hq[q], IW9[q], S::kLocalRef ? v : 0.f);
+        return;
+    }
+    const bool flow = d.npop == 23;
+    float ux = 0.f, uy = 0.f;
+    if (flow) {
+        float f[9], g[5], h[9];
+        decode_cell<S>(d, par, x, y, true, f, g, h);
+        double p = 0.0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) p += (double)h[q];
+        const float pc = fminf(fmaxf((float)p, -1.f), 1.f);
+        const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+        const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
+        const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
+        ux = ((f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7])) * sc;
+        uy = ((f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8])) * sc;
+    }
+    float gq[5];
+#pragma unroll
+    for (int q = 1; q < 5; ++q) gq[q] = W5[q] * v * (1.f + 3.f * (CX[q] * ux + CY[q] * uy));
+    gq[0] = v - ((gq[1] + gq[2]) + (gq[3] + gq[4]));
+    if (S::kLocalRef) ((GMEM typename S::T*)(d.refs[par]))[i] = S::to_ref(0.f);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        float r[4] = {0.f, 0.f, 0.f, 0.f};
+        if (S::kLocalRef && d.inout && x - CX[q] < 0) ref_at<S>(d, par, -1, y - CY[q], r);  // ghost constants
+        plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], r[R_U]);
+    }
+}
+
+template <class S>
+static hipError_t write_field_s(const DomDesc& d, int par, int field, const float* src, hipStream_t s) {
+    dim3 grid((d.nx + 255) / 256, d.ny);
+    hipLaunchKernelGGL(k_write_field<S>, grid, dim3(256), 0, s, d, par, field, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_write_field(const DomDesc& d, int par, int field, const float* src, hipStream_t s) {
+    switch (d.storage) {
+        case 0: return write_field_s<StoreF32>(d, par, field, src, s);
+        case 1: return write_field_s<StoreF16>(d, par, field, src, s);
+        case 2: return write_field_s<StoreBF16>(d, par, field, src, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------------------------
 // population sets <-> canonical FP32 [q][y][x]
 template <class S>
 __global__ void k_pop_get(DomDesc d, int par, int set, float* __restrict__ canon) {

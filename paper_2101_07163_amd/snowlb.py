@@ -63,6 +63,7 @@ _SIGS = {
     "snowlb_read": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
     "snowlb_read_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
     "snowlb_write_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb_write_field": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
     "snowlb_diag": (ctypes.c_int32, [_v, _P(ctypes.c_double), _v]),
     "snowlb_state_bytes": (ctypes.c_int64, [_v]),
     "snowlb_save_state": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
@@ -170,6 +171,10 @@ def snowlb_read_populations(ctx, pset: int, dst_dev: int, elems: int, stream: in
 
 def snowlb_write_populations(ctx, pset: int, src_dev: int, elems: int, stream: int) -> None:
     _check(lib().snowlb_write_populations(ctx, pset, src_dev, elems, stream), ctx)
+
+
+def snowlb_write_field(ctx, field: int, src_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb_write_field(ctx, field, src_dev, elems, stream), ctx)
 
 
 def snowlb_diag(ctx, stream: int) -> tuple[int, list]:
@@ -363,6 +368,13 @@ class Sim:
         out = self.torch.empty((q,) + self.shape, dtype=self.torch.float32, device="cuda")
         snowlb_read_populations(self.ctx, pset, out.data_ptr(), out.numel(), self.stream)
         return out if q > 1 else out[0]
+
+    def write_field(self, field: str, values):
+        """Overwrite phi (h = w phi, phi_prev = phi) or U (g at the equilibrium with the current velocity)."""
+        t = self.torch.as_tensor(values, dtype=self.torch.float32, device="cuda").reshape(self.shape).contiguous()
+        snowlb_write_field(self.ctx, FIELDS[field], t.data_ptr(), t.numel(), self.stream)
+        self.torch.cuda.current_stream().synchronize()
+        return self
 
     def write_populations(self, name: str, values):
         pset, q = POPS[name]

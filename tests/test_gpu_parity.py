@@ -403,6 +403,36 @@ def test_ventilated_512_long_run(storage):
         assert errs["phi"] <= 1e-1
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_write_field_sets_a_consistent_state(storage):
+    """snowlb_write_field on a ventilated lattice: phi and U read back within the storage rounding,
+    and the state left behind steps like the FP64 oracle started from the same populations (read
+    back through the C ABI).  Fields other than phi and U are rejected."""
+    cfg = dict(W.C3)
+    cfg.update(nx=96, ny=80, seed=(30.0, 40.0, 6.0))
+    sim = S.Sim(cfg, storage=storage).init().step(20)
+    yy, xx = np.mgrid[0:80, 0:96]
+    phi = np.tanh((8.0 - np.hypot(xx - 50.3, yy - 39.6)) / np.sqrt(2.0)).astype(np.float32)
+    U = (0.4 + 0.1 * np.sin(2 * np.pi * xx / 96) * np.cos(2 * np.pi * yy / 80)).astype(np.float32)
+    sim.write_field("phi", phi).write_field("U", U)
+    tol = {"fp32": 1e-6, "fp16": 2e-3, "bf16": 2e-2}[storage]
+    e_phi = float(np.abs(sim.read("phi").cpu().numpy() - phi).max())
+    e_U = float(np.abs(sim.read("U").cpu().numpy() - U).max())
+    report("write_field %s phi" % storage, e_phi)
+    report("write_field %s U" % storage, e_U)
+    assert e_phi < tol and e_U < tol
+    st = {k: sim.read_populations(k).double().cpu().numpy() for k in ("f", "g", "h", "phip")}
+    o = oracle.Oracle(oracle.Params.from_dict(cfg)).set_state(**st)
+    o.step(20)
+    sim.step(20)
+    F = o.fields()
+    err = max(float(np.abs(sim.read(k).double().cpu().numpy() - F[k]).max()) for k in ("phi", "U", "rho"))
+    report("write_field %s then 20 steps" % storage, err)
+    assert err < {"fp32": 1e-5, "fp16": 5e-3, "bf16": 5e-2}[storage]
+    with pytest.raises(S.SnowlbError):
+        sim.write_field("rho", phi)
+
+
 @pytest.mark.slow
 def test_c2_ventilated_1024_checkpoints():
     """The 1024^2 ventilated workload (inlet u = 0.02, U_in = U0 = 0.6, seed R = 8 at (300, 512),
