@@ -41,10 +41,10 @@ def bytes_per_update(flow: bool, storage: str) -> int:
 
 
 def kernel_source_sha() -> str:
-    """Hash of the step kernel's code (its source and the shared header it indexes memory with),
-    comments and blank space removed, so that only a change of code marks counters as stale."""
+    """Hash of the step kernel's code (its source and the two headers it is built from), comments and
+    blank space removed, so that only a change of that code marks counters as stale."""
     h = hashlib.sha256()
-    for name in ("snowlb_kernels.hip", "snowlb_internal.h"):
+    for name in ("snowlb_kernels.hip", "snowlb_device.h", "snowlb_internal.h"):
         for line in open(os.path.join(ROOT, "paper_2101_07163_amd", "csrc", name)):
             code = line.split("//", 1)[0].strip()
             if code:
