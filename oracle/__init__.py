@@ -38,12 +38,12 @@ def build(force: bool = True) -> str:
 class OrcParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("flow", ctypes.c_int32),
-        ("inout", ctypes.c_int32), ("n_fold", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("inout", ctypes.c_int32), ("n_fold", ctypes.c_int32), ("stencil", ctypes.c_int32),
         ("eps", ctypes.c_double), ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
         ("lam", ctypes.c_double), ("L_sat", ctypes.c_double), ("tau_vap", ctypes.c_double),
         ("tau_f", ctypes.c_double), ("h_drag", ctypes.c_double), ("kappa_N", ctypes.c_double),
         ("rho0", ctypes.c_double), ("u_in", ctypes.c_double), ("U_in", ctypes.c_double),
-        ("grad_eps2", ctypes.c_double),
+        ("grad_eps2", ctypes.c_double), ("symmetric", ctypes.c_int32), ("pad_", ctypes.c_int32),
     ]
 
 
@@ -93,6 +93,8 @@ class Params:
     flow: int = 0
     inout: int = 0
     n_fold: int = 6
+    stencil: int = 4      # isotropic gradient: 2 (central difference), 4, 6, 8 (Table 1)
+    symmetric: int = 0    # 1: diffusivity q = 1 in both phases (thermal model of Sec. 3.1.1)
     eps: float = 0.05
     W0: float = 1.0
     tau0: float = 10.0

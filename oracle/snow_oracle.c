@@ -15,11 +15,13 @@
  *
  * Readings of points where the paper is silent or ambiguous are marked [Rk] and listed, with their
  * justification, in the design notes that ship with the repository:
- *   R1  gradient: grad phi = sum_c w(|c|^2) phi(x+c) c with the Table 1 E4 weights and no 1/cs^2
+ *   R1  gradient: grad phi = sum_c w(|c|^2) phi(x+c) c with the Table 1 weights and no 1/cs^2
  *       (the Table 1 weights already satisfy sum w c c = I; with 1/cs^2 the gradient of x would be 3).
+ *       E2 is the central difference of the same section (w(1) = 1/2); E4 is the default.
  *   R2  anisotropic flux N = kappa_N * (W0^2/tau0) * |grad phi|^2 * a * da/d(grad phi); kappa_N = 1
  *       is the variational form, kappa_N = 2 the literal d(a^2)/d(grad phi) of Eq. (e).
- *   R3  vapour diffusivity switch q = (1 - phi)/2 clamped to [0, 1], tau_g = 1/2 + (tau_vap - 1/2) q.
+ *   R3  vapour diffusivity switch q = (1 - phi)/2 clamped to [0, 1], tau_g = 1/2 + (tau_vap - 1/2) q;
+ *       the symmetric (thermal) variant of the Sec. 3.1.1 study takes q = 1 in both phases.
  *   R4  flow: second-order equilibrium, Guo forcing, eta_f = nu; the projected velocity
  *       u = (1 - phi)/2 * j / (rho + k/2) is used in f_eq, in the drag force and in g_eq; phi is
  *       clamped to [-1, 1] inside the projection and drag factors.
@@ -52,7 +54,12 @@ static const double W9[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 
 static const double W5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
 static const double CS2 = 1.0 / 3.0;
 /* Table 1, E4 row: w(1) for the four |c|^2 = 1 neighbours, w(2) for the four |c|^2 = 2 ones. */
-static const double E4_W[3] = {0.0, 1.0 / 3.0, 1.0 / 12.0};
+/* Table 1 (Sec. 3.1.1): weight of a stencil vector c by |c|^2 = 0..8, for E4, E6 and E8; E2 is the
+ * central difference of the same section. */
+static const double E2_W[9] = {0.0, 1.0 / 2.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+static const double E4_W[9] = {0.0, 1.0 / 3.0, 1.0 / 12.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+static const double E6_W[9] = {0.0, 4.0 / 15.0, 1.0 / 10.0, 0.0, 1.0 / 120.0, 0.0, 0.0, 0.0, 0.0};
+static const double E8_W[9] = {0.0, 4.0 / 21.0, 4.0 / 45.0, 0.0, 1.0 / 60.0, 2.0 / 315.0, 0.0, 0.0, 1.0 / 5040.0};
 
 struct orc {
     orc_params p;
@@ -149,16 +156,30 @@ static double phi_at(const orc_params* p, const double* phi, int x, int y)
     return phi[cell(p, x, y)];
 }
 
-/* Isotropic gradient, E4 stencil (Sec. 3.1.1, Table 1) [R1]. */
+static const double* stencil_weights(const orc_params* p)
+{
+    switch (p->stencil) {
+        case 2: return E2_W;
+        case 6: return E6_W;
+        case 8: return E8_W;
+        default: return E4_W;
+    }
+}
+
+/* Isotropic gradient (Sec. 3.1.1, Table 1) [R1]: every vector c with |c| <= 2 sqrt 2 whose layer
+ * |c|^2 has a weight in the chosen stencil. */
 static void grad_at(const orc_params* p, const double* phi, int x, int y, double* gx, double* gy)
 {
+    const double* W = stencil_weights(p);
     double sx = 0.0, sy = 0.0;
-    for (int q = 1; q < 9; ++q) {
-        double w = E4_W[CX[q] * CX[q] + CY[q] * CY[q]];
-        double v = phi_at(p, phi, x + CX[q], y + CY[q]);
-        sx += w * CX[q] * v;
-        sy += w * CY[q] * v;
-    }
+    for (int cy = -2; cy <= 2; ++cy)
+        for (int cx = -2; cx <= 2; ++cx) {
+            double w = W[cx * cx + cy * cy];
+            if (w == 0.0) continue;
+            double v = phi_at(p, phi, x + cx, y + cy);
+            sx += w * cx * v;
+            sy += w * cy * v;
+        }
     *gx = sx;
     *gy = sy;
 }
@@ -176,6 +197,8 @@ void orc_grad(const orc_params* p, const double* phi, double* gx, double* gy)
 orc* orc_create(const orc_params* p)
 {
     if (!p || p->nx < 1 || p->ny < 1) return NULL;
+    if (p->stencil != 0 && p->stencil != 2 && p->stencil != 4 && p->stencil != 6 && p->stencil != 8) return NULL;
+    if (p->symmetric != 0 && p->symmetric != 1) return NULL;
     orc* o = (orc*)calloc(1, sizeof(orc));
     if (!o) return NULL;
     o->p = *p;
@@ -314,7 +337,7 @@ static void collide(orc* o, int x, int y)
     o->uy[i] = uy;
 
     /* vapour advection-diffusion-reaction (Sec. 2.2.2) [R3, R7] */
-    double qd = clampd(0.5 * (1.0 - phi), 0.0, 1.0);
+    double qd = p->symmetric ? 1.0 : clampd(0.5 * (1.0 - phi), 0.0, 1.0);
     double tau_g = 0.5 + (p->tau_vap - 0.5) * qd;
     double geq[5];
     orc_geq(U, ux, uy, geq);

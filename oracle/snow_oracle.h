@@ -24,7 +24,8 @@ typedef struct {
     int32_t inout;    /* 0: periodic in x; 1: fixed-velocity inlet at x = 0, zero-gradient outlet
                          at x = nx-1 (Sec. 3.1.3, 3.2.2); y is always periodic                  */
     int32_t n_fold;   /* symmetry of the anisotropy function: 6 (Sec. 2.1) or 4 (Sec. 3.1.2)     */
-    int32_t pad_;
+    int32_t stencil;  /* isotropic gradient of Sec. 3.1.1: 2 (central difference), 4, 6 or 8
+                         (the E4, E6, E8 weights of Table 1); 0 means 4                            */
     double eps;       /* anisotropy strength epsilon_xy                                         */
     double W0, tau0;  /* interface width and characteristic time                                */
     double lambda;    /* phase / supersaturation coupling                                        */
@@ -35,6 +36,9 @@ typedef struct {
     double kappa_N;   /* factor on the anisotropic flux: 1 = a da/dgrad(phi), 2 = d(a^2)/dgrad   */
     double rho0, u_in, U_in;  /* inlet state (density, x-velocity, supersaturation)             */
     double grad_eps2; /* |grad phi|^2 below which the normal is undefined (a = 1, N = 0)          */
+    int32_t symmetric; /* 0: diffusivity switch q(phi) = (1 - phi)/2 of Eq. (b) (vapour, one-sided);
+                          1: q = 1 in both phases (the thermal model of the Sec. 3.1.1 study)       */
+    int32_t pad_;
 } orc_params;
 
 typedef struct orc orc;
@@ -68,10 +72,10 @@ void orc_feq(double rho, double ux, double uy, double out[9]);
 void orc_geq(double U, double ux, double uy, double out[5]);
 void orc_guo(const orc_params* p, double ux, double uy, double Fx, double Fy, double out[9]);
 void orc_aniso(const orc_params* p, double gx, double gy, double* a, double* Nx, double* Ny);
-/* E4 gradient of phi[y*nx+x] with the boundary ghosts of this parameter set. */
+/* Isotropic gradient (the stencil of this parameter set) of phi[y*nx+x] with its boundary ghosts. */
 void orc_grad(const orc_params* p, const double* phi, double* gx, double* gy);
 
-/* Discrete adjoint (no flow, periodic): runs n steps from the seed with the per-cell initial
+/* Discrete adjoint (no flow, periodic, E4 gradient, one-sided diffusivity): runs n steps from the seed with the per-cell initial
  * supersaturation U_init, evaluates L = sum (phi_T - phi_target)^2, and returns L together with
  * dL/dU_init (ny*nx) and dL/deps, propagated backwards from checkpoints every `stride` steps
  * (0: ceil(sqrt(n))).  phiT_out (optional) receives phi_T.  NaN on invalid input. */

@@ -238,7 +238,8 @@ double orc_adj_run(const orc_params* p, double xs, double ys, double R, double w
                    const double* phi_target, int32_t nsteps, int32_t stride, double* dL_dUinit, double* dL_deps,
                    double* phiT_out)
 {
-    if (!p || p->flow || p->inout || nsteps < 0) return NAN;
+    if (!p || p->flow || p->inout || nsteps < 0 || (p->stencil != 0 && p->stencil != 4) || p->symmetric)
+        return NAN;
     const int64_t n = (int64_t)p->nx * p->ny;
     int s = stride > 0 ? stride : (int)ceil(sqrt((double)(nsteps > 0 ? nsteps : 1)));
     int nck = nsteps > 0 ? (nsteps + s - 1) / s : 1;

@@ -60,6 +60,10 @@ def test_table1_isotropy_orders():
     1/cs^2 prefactor), has 4th-order isotropy (c_x^4 : c_x^2 c_y^2 = 3), and E6/E8 also have 6th-order
     isotropy (c_x^6 : c_x^4 c_y^2 = 5) which E4 lacks."""
     tab = json.load(open(os.path.join(GOLDEN, "table1_isotropic_weights.json")))
+    # the central difference of the same section, E2: normalised like the others, not isotropic
+    e2 = [(1, 0, 1), (-1, 0, 1), (0, 1, 1), (0, -1, 1)]
+    m2 = lambda px, py: sum(Fraction(1, 2) * Fraction(i) ** px * Fraction(j) ** py for i, j, k in e2)
+    assert m2(2, 0) == 1 and m2(1, 1) == 0 and m2(4, 0) != 3 * m2(2, 2)
     for name in ("E4", "E6", "E8"):
         w = {int(k): Fraction(v) for k, v in tab[name].items()}
         vecs = _stencil(w.keys())
@@ -79,33 +83,99 @@ def _poly_grid(n=16):
     return x, y
 
 
-def test_gradient_exact_on_linear_and_quadratic():
+@pytest.mark.parametrize("stencil", [2, 4, 6, 8])
+def test_gradient_exact_on_linear_and_quadratic(stencil):
     n = 16
-    p = oracle.Params(nx=n, ny=n)
+    p = oracle.Params(nx=n, ny=n, stencil=stencil)
     x, y = _poly_grid(n)
     cases = [(0.3 * x - 0.7 * y + 2, 0.3 + 0 * x, -0.7 + 0 * x),
              (x * x + 2 * x * y - 0.5 * y * y, 2 * x + 2 * y, 2 * x - y)]
-    inner = (slice(2, n - 2), slice(2, n - 2))
+    inner = (slice(3, n - 3), slice(3, n - 3))
     for phi, ex, ey in cases:
         gx, gy = oracle.grad(p, phi)
         assert np.abs(gx - ex)[inner].max() < 1e-12
         assert np.abs(gy - ey)[inner].max() < 1e-12
 
 
-def test_gradient_e4_error_is_isotropic_on_cubics():
-    """On cubic fields the E4 error is exactly (1/6) grad(laplacian phi)."""
+def _table1_A(name):
+    """sum w c_x^2 c_y^2 of a Table 1 row (the 4th-order isotropic tensor's coefficient), exact."""
+    tab = json.load(open(os.path.join(GOLDEN, "table1_isotropic_weights.json")))
+    w = {int(k): Fraction(v) for k, v in tab[name].items()}
+    return sum(w[k] * Fraction(i * i * j * j) for i, j, k in _stencil(w.keys()))
+
+
+@pytest.mark.parametrize("stencil", [2, 4, 6, 8])
+def test_gradient_error_on_cubics(stencil):
+    """On a cubic field the stencil sum is the gradient plus its third-order Taylor term, exactly:
+    for a 4th-order isotropic stencil (E4, E6, E8) that term is (A/2) grad(laplacian phi) with
+    A = sum w c_x^2 c_y^2 taken from the Table 1 fixture (1/3, 2/5, 4/7), isotropic; for the
+    central difference E2 it is (1/6)(d^3 phi/dx^3, d^3 phi/dy^3), which depends on the axes."""
     n = 16
-    p = oracle.Params(nx=n, ny=n)
+    p = oracle.Params(nx=n, ny=n, stencil=stencil)
     x, y = _poly_grid(n)
     phi = x ** 3 - 2 * x * y * y + 0.5 * y ** 3 + x * x * y
     ex = 3 * x * x - 2 * y * y + 2 * x * y
     ey = -4 * x * y + 1.5 * y * y + x * x
-    # laplacian = 6x - 4x + 3y + 2y = 2x + 5y, whose gradient is (2, 5)
-    dlx, dly = 2.0 + 0 * x, 5.0 + 0 * x
-    inner = (slice(2, n - 2), slice(2, n - 2))
+    if stencil == 2:
+        dx, dy = 6.0 / 6, 3.0 / 6   # third derivatives 6 and 3
+    else:
+        # laplacian = 6x - 4x + 3y + 2y = 2x + 5y, whose gradient is (2, 5)
+        A = float(_table1_A("E%d" % stencil))
+        dx, dy = A / 2 * 2.0, A / 2 * 5.0
+    inner = (slice(3, n - 3), slice(3, n - 3))
     gx, gy = oracle.grad(p, phi)
-    assert np.abs(gx - ex - dlx / 6)[inner].max() < 1e-10
-    assert np.abs(gy - ey - dly / 6)[inner].max() < 1e-10
+    assert np.abs(gx - ex - dx)[inner].max() < 1e-10
+    assert np.abs(gy - ey - dy)[inner].max() < 1e-10
+    if stencil == 4:
+        assert abs(dx - 2.0 / 6) < 1e-15   # the familiar (1/6) grad(laplacian) of E4
+
+
+def test_gradient_higher_isotropy_on_quintics():
+    """E6 and E8 are 6th-order isotropic (Table 1), E4 is not.  For phi = s^5 with s = n . x the
+    stencil error along n is, exactly, 30 A s^2 (the 4th-order term, A from the fixture) plus the
+    constant M6(n) = sum w (c . n)^6 (the 6th-order term).  Check that the oracle's error minus the
+    first term is that constant over the grid, and that M6 is the same at 0 and 30 degrees for E6
+    and E8 and differs for E4."""
+    n = 16
+    x, y = _poly_grid(n)
+    x = x - n / 2
+    y = y - n / 2
+    inner = (slice(3, n - 3), slice(3, n - 3))
+
+    def m6(stencil, t):
+        c, s_ = math.cos(t), math.sin(t)
+        s = x * c + y * s_
+        gx, gy = oracle.grad(oracle.Params(nx=n, ny=n, stencil=stencil), s ** 5)
+        A = float(_table1_A("E%d" % stencil))
+        e = (gx * c + gy * s_ - 5 * s ** 4 - 30 * A * s ** 2)[inner]
+        assert e.max() - e.min() < 1e-8, (stencil, t, e.max() - e.min())
+        return e.mean()
+
+    for stencil, iso in ((4, False), (6, True), (8, True)):
+        d = abs(m6(stencil, 0.0) - m6(stencil, math.pi / 6))
+        if iso:
+            assert d < 1e-9, (stencil, d)
+        else:
+            assert d > 1e-2, (stencil, d)
+
+
+@pytest.mark.parametrize("stencil", [6, 8])
+def test_gradient_boundary_ghosts_two_cells(stencil):
+    """The two-cell stencils see the same closure two cells deep: phi = -1 at x = -1 and x = -2
+    (inlet), phi(nx-1) at x = nx and nx + 1 (outlet), y periodic (weights from the Table 1 fixture)."""
+    nx, ny = 7, 6
+    p = oracle.Params(nx=nx, ny=ny, inout=1, flow=1, stencil=stencil)
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(-1, 1, (ny, nx))
+    gx, gy = oracle.grad(p, phi)
+    tab = json.load(open(os.path.join(GOLDEN, "table1_isotropic_weights.json")))
+    w = {int(k): Fraction(v) for k, v in tab["E%d" % stencil].items()}
+    ph = lambda xx, yy: -1.0 if xx < 0 else phi[yy % ny, min(xx, nx - 1)]
+    for xx in (0, 1, nx - 2, nx - 1):
+        for yy in (0, ny - 1):
+            wx = sum(float(w[k]) * i * ph(xx + i, yy + j) for i, j, k in _stencil(w.keys()))
+            wy = sum(float(w[k]) * j * ph(xx + i, yy + j) for i, j, k in _stencil(w.keys()))
+            assert abs(gx[yy, xx] - wx) < 1e-13 and abs(gy[yy, xx] - wy) < 1e-13
 
 
 def test_gradient_boundary_ghosts():
@@ -247,6 +317,40 @@ def test_gaussian_advection_diffusion(u):
     s2_bad = sigma0 ** 2 + 2 * (tau_g / 3) * T
     Ub = 0.5 + 0.1 * sigma0 ** 2 / s2_bad * np.exp(-(dx ** 2 + dy ** 2) / (2 * s2_bad))
     assert np.sqrt(np.sum((Un - Ub) ** 2) / np.sum((Ub - 0.5) ** 2)) > 10 * err
+
+
+def test_symmetric_diffusivity_inside_the_solid():
+    """Thermal variant of the Sec. 3.1.1 study (diffusivity q = 1 in both phases): inside ice
+    (phi = 1 everywhere, a fixed point of the phase field) a Gaussian pulse of U spreads with
+    D = cs^2 (tau_vap - 1/2) as in the fluid.  The one-sided switch of Eq. (b) gives the solid
+    tau_g = 1/2, i.e. D = 0, and the pulse keeps nearly all of its height."""
+    n, sigma0, T, tau_g = 96, 6.0, 400, 0.8
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    U = 0.5 + 0.1 * np.exp(-((x - n / 2) ** 2 + (y - n / 2) ** 2) / (2 * sigma0 ** 2))
+    peak = {}
+    for sym in (1, 0):
+        p = oracle.Params(nx=n, ny=n, tau_vap=tau_g, L_sat=1.0, symmetric=sym)
+        o = oracle.Oracle(p)
+        o.set_state(g=W5()[:, None, None] * U[None], h=W9()[:, None, None] * np.ones((9, n, n)),
+                    phip=np.ones((n, n)))
+        o.step(T)
+        F = o.fields()
+        assert np.abs(F["phi"] - 1).max() < 1e-13
+        Un = F["U"]
+        peak[sym] = Un.max() - 0.5
+        if sym:
+            D = (tau_g - 0.5) / 3
+            s2 = sigma0 ** 2 + 2 * D * T
+            Ua = 0.5 + 0.1 * sigma0 ** 2 / s2 * np.exp(-((x - n / 2) ** 2 + (y - n / 2) ** 2) / (2 * s2))
+            assert np.sqrt(np.sum((Un - Ua) ** 2) / np.sum((Ua - 0.5) ** 2)) < 3e-3
+    assert peak[1] < 0.4 * 0.1 and peak[0] > 0.8 * 0.1, peak
+
+
+def test_invalid_stencil_rejected():
+    with pytest.raises(ValueError):
+        oracle.Oracle(oracle.Params(nx=8, ny=8, stencil=3))
+    with pytest.raises(ValueError):
+        oracle.Oracle(oracle.Params(nx=8, ny=8, symmetric=2))
 
 
 def _slab(W0, U0, theta, n, eps=0.05, lam=3.0, half=8.0, L_sat=0.0):
