@@ -108,6 +108,27 @@ def bw_probe(S, torch, nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def stencil_family(S, torch, W, cfg, storage, steps, tile):
+    """The gradient-stencil family of Sec. 3.1.1 on the headline workload (same bytes per update;
+    E6 and E8 stage a two-cell halo) and on the stencil-study workload (800^2, thermal model), MLUPS."""
+    cells = cfg["nx"] * cfg["ny"]
+    bpu = bytes_per_update(bool(cfg.get("flow", 0)), storage)
+    res = {"workload": cfg["name"], "storage": storage}
+    for st in (2, 4, 6, 8):
+        sim, wall, k_ms, _ = time_steps(S, torch, dict(cfg, stencil=st), storage, steps, 50, tile)
+        res["E%d" % st] = {"MLUPS": round(cells * steps / wall / 1e6, 1), "kernel_avg_ms": round(k_ms, 5),
+                           "GBps_algorithmic": round(cells * bpu / (k_ms * 1e-3) / 1e9, 1)}
+        del sim
+    study = {"workload": W.F1["name"], "steps": 20000}
+    for st in (2, 4, 6, 8):
+        c = dict(W.F1, stencil=st)
+        sim, wall, k_ms, _ = time_steps(S, torch, c, "fp32", 20000, 200, tile)
+        study["E%d_MLUPS" % st] = round(c["nx"] * c["ny"] * 20000 / wall / 1e6, 1)
+        del sim
+    res["study"] = study
+    return res
+
+
 def batch_sweep(S, torch, W, steps=200, warmup=20, solo_steps=64):
     """The 64-crystal sweep as one batch (one launch per step over all tiles) against the same work
     done crystal by crystal (solo contexts, graph-replayed), both in aggregate MLUPS."""
@@ -213,7 +234,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5",
+    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5,stencils",
                     help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16, "
                          "c4 (64-crystal batch), c5 (adjoint/forward time ratio)")
     args = ap.parse_args()
@@ -291,6 +312,9 @@ def main():
                                          "bytes_per_update": b2}
             log("%s storage: %s" % (st, extras["%s_storage" % st]))
             del s2
+        if "stencils" in wanted:
+            extras["stencils"] = stencil_family(S, torch, W, cfg, args.storage, min(args.steps, 1000), args.tile)
+            log("gradient stencils: %s" % extras["stencils"])
         if "c4" in wanted:
             extras["c4_batch"] = batch_sweep(S, torch, W)
             log("64-crystal batch: %s" % extras["c4_batch"])

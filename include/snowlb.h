@@ -99,6 +99,12 @@ typedef struct {
     double init_width;  /* width of the tanh seed profile (cells)                                 */
     int32_t diag_every; /* >0: snowlb_step checks for non-finite values every this many steps     */
     int32_t tile;       /* step-kernel tile configuration; -1 = autotune, 0 = default            */
+    int32_t stencil;    /* isotropic gradient of phi (Sec. 3.1.1): 4 = E4 (default), 6 = E6, 8 = E8
+                           (Table 1 weights), 2 = E2 (the central difference of the same section);
+                           E6 and E8 reach two cells and stage a two-cell halo                      */
+    int32_t symmetric;  /* 0: diffusivity switch q(phi) = (1 - phi)/2 of Eq. (b) (vapour, no
+                           diffusion in the ice); 1: q = 1 in both phases (the symmetric thermal
+                           model of the Sec. 3.1.1 stencil study)                                   */
 } snowlb_params;
 
 typedef struct snowlb_ctx snowlb_ctx;
@@ -178,7 +184,8 @@ snowlb_status snowlb_set_grid_mode(snowlb_ctx* ctx, int32_t grid_mode);
 int32_t snowlb_get_grid_mode(const snowlb_ctx* ctx);
 
 /* ---------------------------------------------------------------------------------------------
- * Discrete adjoint (contexts with flow = 0, periodic x, FP32 storage; EUNSUPPORTED otherwise).
+ * Discrete adjoint (contexts with flow = 0, periodic x, FP32 storage, stencil 4 and symmetric = 0;
+ * EUNSUPPORTED otherwise).
  *
  * snowlb_adj_forward runs n >= 1 steps from the current state (normally right after snowlb_init),
  * keeping a checkpoint of the state every ckpt_stride steps (0: ceil(sqrt(n))); afterwards the
@@ -197,13 +204,13 @@ snowlb_status snowlb_set_eps(snowlb_ctx* ctx, double eps);
 /* ---------------------------------------------------------------------------------------------
  * Batches: many independent crystals (each its own lattice size and parameters) advanced together,
  * one launch per step over the tiles of all domains, replayed from a captured HIP graph.  All
- * domains must share flow, bc_x, storage and n_fold (they select the kernel); everything else may
- * differ.  Each domain evolves exactly as a context created from the same parameters would
+ * domains must share flow, bc_x, storage, n_fold and the reach of the stencil (E2/E4 or E6/E8;
+ * they select the kernel); everything else may differ.  Each domain evolves exactly as a context created from the same parameters would
  * (bitwise: same kernel, same per-domain arithmetic). */
 typedef struct snowlb_batch snowlb_batch;
 
 /* Create a batch of n >= 1 domains from params[0..n-1] (validated like snowlb_create; EINVAL if
- * they do not share flow, bc_x, storage and n_fold).  *out is NULL on failure. */
+ * they do not share flow, bc_x, storage, n_fold and the stencil reach).  *out is NULL on failure. */
 snowlb_status snowlb_batch_create(const snowlb_params* params, int32_t n, snowlb_batch** out);
 void snowlb_batch_destroy(snowlb_batch* b);
 int32_t snowlb_batch_size(const snowlb_batch* b);

@@ -59,7 +59,7 @@ snowlb_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SNOWL
 struct Driver {
     const DomDesc* d_doms = nullptr;  // owned by the caller
     std::vector<const DomDesc*> h_doms;  // host copies (geometry for the tile lists)
-    int storage = 0, flow = 0, inout = 0;
+    int storage = 0, flow = 0, inout = 0, rad = 1;
     int tile = 0, grid_mode = 0;
     std::vector<TileDesc*> d_tiles;
     std::vector<int> ntiles;
@@ -131,9 +131,9 @@ struct Driver {
     snowlb_status plain(int cfg, int mode, int n, hipStream_t s) {
         snowlb_status st = ensure_tiles(cfg);
         if (st) return st;
-        const int grid = step_grid(cfg, ntiles[cfg], storage, flow, inout, mode);
+        const int grid = step_grid(cfg, ntiles[cfg], storage, flow, inout, rad, mode);
         for (int i = 0; i < n; ++i) {
-            hipError_t e = launch_step(cfg, storage, flow, inout, d_doms, d_tiles[cfg], ntiles[cfg], grid, par, s);
+            hipError_t e = launch_step(cfg, storage, flow, inout, rad, d_doms, d_tiles[cfg], ntiles[cfg], grid, par, s);
             if (e != hipSuccess) return hipfail(e, "step kernel launch");
             par ^= 1;
             step += 1;
@@ -143,12 +143,13 @@ struct Driver {
 
     snowlb_status build_graph(int K) {
         drop_graph();
-        const int grid = step_grid(tile, ntiles[tile], storage, flow, inout, grid_mode);
+        const int grid = step_grid(tile, ntiles[tile], storage, flow, inout, rad, grid_mode);
         hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "hipStreamBeginCapture");
         hipError_t le = hipSuccess;
         for (int i = 0; i < K && le == hipSuccess; ++i)
-            le = launch_step(tile, storage, flow, inout, d_doms, d_tiles[tile], ntiles[tile], grid, i & 1, cap_stream);
+            le = launch_step(tile, storage, flow, inout, rad, d_doms, d_tiles[tile], ntiles[tile], grid, i & 1,
+                             cap_stream);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cap_stream, &g);
         if (le != hipSuccess) {
@@ -303,7 +304,8 @@ void tune_store(const std::string& key, int tile, int mode) {
 
 std::string tune_key(const snowlb_params& p) {
     char b[128];
-    std::snprintf(b, sizeof b, "%s %d %d %d %d %d", kTuneLayout, p.nx, p.ny, p.storage, p.flow, p.bc_x);
+    std::snprintf(b, sizeof b, "%s %d %d %d %d %d r%d", kTuneLayout, p.nx, p.ny, p.storage, p.flow, p.bc_x,
+                  stencil_reach(p.stencil));
     return b;
 }
 
@@ -330,6 +332,9 @@ const char* validate_msg(const snowlb_params* p) {
     if (p->bc_x == SNOWLB_BC_INOUT && !p->flow) return "inflow/outflow needs flow = 1";
     if (p->storage < 0 || p->storage > 2) return "unknown storage";
     if (p->n_fold != 6 && p->n_fold != 4) return "n_fold must be 6 or 4";
+    if (p->stencil != 2 && p->stencil != 4 && p->stencil != 6 && p->stencil != 8)
+        return "stencil must be 2, 4, 6 or 8";
+    if (p->symmetric != 0 && p->symmetric != 1) return "symmetric must be 0 or 1";
     if (!finite_all(p)) return "non-finite parameter";
     if (p->eps < 0 || p->eps >= 0.5) return "eps must lie in [0, 0.5)";
     if (p->W0 <= 0 || p->tau0 <= 0) return "W0 and tau0 must be > 0";
@@ -452,6 +457,15 @@ void fill_dom(snowlb_ctx* c) {
         d.df_in[q] = (float)(kW9[q] * (p.rho0 - 1.0 + p.rho0 * (3.0 * cu + 4.5 * cu * cu - 1.5 * u * u)));
     }
     for (int q = 0; q < 5; ++q) d.g_in[q] = (float)(kW5[q] * p.U_in * (1.0 + 3.0 * kCX[q] * u));
+    d.sym = p.symmetric;
+    d.stencil = p.stencil;
+    // gradient weights by layer |c|^2 = 1, 2, 4, 5, 8: Table 1 (E4, E6, E8) and the central difference
+    static const double kGW[4][5] = {{1.0 / 2.0, 0.0, 0.0, 0.0, 0.0},
+                                     {1.0 / 3.0, 1.0 / 12.0, 0.0, 0.0, 0.0},
+                                     {4.0 / 15.0, 1.0 / 10.0, 1.0 / 120.0, 0.0, 0.0},
+                                     {4.0 / 21.0, 4.0 / 45.0, 1.0 / 60.0, 2.0 / 315.0, 1.0 / 5040.0}};
+    const int row = p.stencil / 2 - 1;
+    for (int k = 0; k < 5; ++k) d.gw[k] = kGW[row][k];
 }
 
 // Allocate and describe one lattice (shared by contexts and batch members).
@@ -624,6 +638,8 @@ void snowlb_params_default(snowlb_params* p) {
     p->bc_x = SNOWLB_BC_PERIODIC;
     p->storage = SNOWLB_STORE_FP32;
     p->n_fold = 6;
+    p->stencil = 4;
+    p->symmetric = 0;
     p->eps = 0.05;
     p->W0 = 1.0;
     p->tau0 = 10.0;
@@ -681,6 +697,7 @@ snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out) {
         c->drv.storage = p->storage;
         c->drv.flow = p->flow;
         c->drv.inout = p->bc_x;
+        c->drv.rad = stencil_reach(p->stencil);
         st = from_driver(c, c->drv.setup());
     }
     if (st) {
@@ -856,8 +873,11 @@ snowlb_status snowlb_set_eps(snowlb_ctx* c, double eps) {
 // ---------------------------------------------------------------------------------------------- adjoint
 
 static snowlb_status adj_check(snowlb_ctx* c) {
-    if (c->p.flow || c->p.bc_x != SNOWLB_BC_PERIODIC || c->p.storage != SNOWLB_STORE_FP32)
-        return fail(c, SNOWLB_EUNSUPPORTED, "the adjoint supports flow = 0, periodic x and FP32 storage");
+    if (c->p.flow || c->p.bc_x != SNOWLB_BC_PERIODIC || c->p.storage != SNOWLB_STORE_FP32 || c->p.stencil != 4 ||
+        c->p.symmetric)
+        return fail(c, SNOWLB_EUNSUPPORTED,
+                    "the adjoint supports flow = 0, periodic x, FP32 storage, the E4 gradient and the one-sided "
+                    "diffusivity");
     return SNOWLB_OK;
 }
 
@@ -942,7 +962,7 @@ static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const la
     HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int i = 0; i + 1 < len && le == hipSuccess; ++i)
-        le = launch_step(D.tile, c->p.storage, 0, 0, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid,
+        le = launch_step(D.tile, c->p.storage, 0, 0, 1, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid,
                          0, cs);
     for (int i = len - 1; i >= 0 && le == hipSuccess; --i) {
         A.st = (const float*)adj_slot(c, c->adj.nck + i);
@@ -1026,7 +1046,7 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     Driver& D = c->drv;
     snowlb_status r = from_driver(c, D.ensure_tiles(D.tile));
     if (r) return r;
-    const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, D.grid_mode);
+    const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, 1, D.grid_mode);
     // Each checkpoint interval: copy its checkpoint into the first segment slot, then replay the
     // captured program of (len - 1) recompute steps and len reverse steps.  At most three distinct
     // programs occur (the shorter last interval, and a full one for each parity of lambda).
@@ -1072,8 +1092,10 @@ snowlb_status snowlb_batch_create(const snowlb_params* params, int32_t n, snowlb
             return fail(nullptr, SNOWLB_EINVAL, "domain " + std::to_string(i) + ": " + m);
         const snowlb_params& a = params[0];
         const snowlb_params& p = params[i];
-        if (p.flow != a.flow || p.bc_x != a.bc_x || p.storage != a.storage || p.n_fold != a.n_fold)
-            return fail(nullptr, SNOWLB_EINVAL, "batch domains must share flow, bc_x, storage and n_fold");
+        if (p.flow != a.flow || p.bc_x != a.bc_x || p.storage != a.storage || p.n_fold != a.n_fold ||
+            stencil_reach(p.stencil) != stencil_reach(a.stencil))
+            return fail(nullptr, SNOWLB_EINVAL,
+                        "batch domains must share flow, bc_x, storage, n_fold and the stencil reach (E2/E4 or E6/E8)");
     }
     snowlb_batch* b = new (std::nothrow) snowlb_batch();
     if (!b) return fail(nullptr, SNOWLB_ENOMEM, "host allocation failed");
@@ -1102,6 +1124,7 @@ snowlb_status snowlb_batch_create(const snowlb_params* params, int32_t n, snowlb
     b->drv.storage = params[0].storage;
     b->drv.flow = params[0].flow;
     b->drv.inout = params[0].bc_x;
+    b->drv.rad = stencil_reach(params[0].stencil);
     snowlb_status st = b->drv.setup();
     if (st) return bail(st, b->drv.err);
     b->drv.tile = params[0].tile >= 0 ? params[0].tile : 0;
@@ -1132,8 +1155,8 @@ snowlb_status snowlb_batch_init(snowlb_batch* b, void* stream) {
 static std::string batch_key(const snowlb_batch* b) {
     const snowlb_params& p = b->doms[0]->p;
     char k[160];
-    std::snprintf(k, sizeof k, "%s batch %d %lld %d %d %d", kTuneLayout, (int)b->doms.size(), (long long)b->cells, p.storage,
-                  p.flow, p.bc_x);
+    std::snprintf(k, sizeof k, "%s batch %d %lld %d %d %d r%d", kTuneLayout, (int)b->doms.size(), (long long)b->cells,
+                  p.storage, p.flow, p.bc_x, stencil_reach(p.stencil));
     return k;
 }
 

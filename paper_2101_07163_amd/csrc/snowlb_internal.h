@@ -81,7 +81,11 @@ struct DomDesc {
     float u_in;         // inlet x-velocity
     float df_in[9];     // inlet ghost populations f_eq(rho0, (u_in, 0)) - w (flow deviations)
     float g_in[5];      // inlet ghost populations g_eq(U_in, (u_in, 0))
-    float pad_[3];
+    int32_t sym;        // 1: vapour diffusivity switch q = 1 in both phases (thermal variant);
+                        // 0: q = (1 - phi)/2 clamped to [0, 1]
+    int32_t stencil;    // isotropic gradient: 2, 4 (one-cell reach) or 6, 8 (two-cell reach)
+    float pad_;
+    double gw[5];       // gradient weights of the layers |c|^2 = 1, 2, 4, 5, 8 (Sec. 3.1.1, Table 1)
 };
 
 struct TileDesc {
@@ -95,12 +99,15 @@ const char* tile_config_name(int i);
 int tile_config_tx(int i);
 int tile_config_ty(int i);
 // One step of every tile in `tiles` (device array of ntiles entries), reading copy `par` and writing
-// copy 1 - par.  `flow`, `inout`, `storage` must be the same for every domain referenced.
-hipError_t launch_step(int tile_cfg, int storage, int flow, int inout, const DomDesc* doms_dev,
+// copy 1 - par.  `flow`, `inout`, `storage` and the gradient reach `rad` (1 for E2/E4, 2 for E6/E8)
+// must be the same for every domain referenced.
+hipError_t launch_step(int tile_cfg, int storage, int flow, int inout, int rad, const DomDesc* doms_dev,
                        const TileDesc* tiles_dev, int ntiles, int grid, int par, hipStream_t s);
 // Grid size of a step launch over `ntiles` tiles: grid_mode 0 = one workgroup per tile,
 // 1 = persistent (one wave of resident workgroups looping over the tiles).
-int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout, int grid_mode);
+int step_grid(int tile_cfg, int ntiles, int storage, int flow, int inout, int rad, int grid_mode);
+// reach of a gradient stencil in cells
+inline int stencil_reach(int stencil) { return stencil >= 6 ? 2 : 1; }
 
 hipError_t launch_init(const DomDesc& d, int par, const float* U_init, float U0, float seed_x,
                        float seed_y, float seed_r, float width, float u_in, hipStream_t s);

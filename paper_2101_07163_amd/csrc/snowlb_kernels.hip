@@ -57,16 +57,17 @@ __device__ __forceinline__ bool map_pos(const DomDesc& d, int gx, int gy, int& s
 
 
 // ---------------------------------------------------------------------------------------------
-// the fused step
-template <int TX, int TY, class S, bool FLOW, bool INOUT>
+// the fused step; RAD is the reach of the gradient stencil (1: E2, E4; 2: E6, E8), i.e. the width of
+// the halo ring staged in LDS
+template <int TX, int TY, class S, bool FLOW, bool INOUT, int RAD>
 __global__ void __launch_bounds__(TX * TY)
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
     constexpr int NR = REF ? (FLOW ? 4 : 1) : 1;  // reference planes staged in LDS
     constexpr int NT = TX * TY;
-    constexpr int LX = TX + 2, LY = TY + 2, LN = LX * LY;
-    constexpr int RING = 2 * LX + 2 * TY;
+    constexpr int LX = TX + 2 * RAD, LY = TY + 2 * RAD, LN = LX * LY;
+    constexpr int RING = LN - NT;
     constexpr int PF = 0, PG = FLOW ? 9 : 0, PH = PG + 5;  // first plane of f, g and h in a copy
     constexpr int NP = (FLOW ? 23 : 14) + (REF ? NR : 0);  // planes per block of a copy (d.nqb)
     constexpr uint32_t ES = sizeof(T);
@@ -76,7 +77,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int own = (ty + 1) * LX + (tx + 1);
+    const int own = (ty + RAD) * LX + (tx + RAD);
     const int npar = 1 - par;
 
     // XCD-aware order (optional): consecutive workgroup ids are spread over the 8 XCDs; give each
@@ -86,11 +87,27 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     const int per_xcd = G / 8;
     const int slot = (xcd_remap && G % 8 == 0) ? ((b % 8) * per_xcd + b / 8) : b;
 
+    // halo position r of the ring: the RAD rows above and below the tile, then RAD columns left and
+    // right of it
     auto ring_pos = [&](int r, int& lx, int& ly) {
-        if (r < LX) { lx = r; ly = 0; }
-        else if (r < 2 * LX) { lx = r - LX; ly = LY - 1; }
-        else if (r < 2 * LX + TY) { lx = 0; ly = 1 + (r - 2 * LX); }
-        else { lx = LX - 1; ly = 1 + (r - 2 * LX - TY); }
+        if constexpr (RAD == 1) {
+            if (r < LX) { lx = r; ly = 0; }
+            else if (r < 2 * LX) { lx = r - LX; ly = LY - 1; }
+            else if (r < 2 * LX + TY) { lx = 0; ly = 1 + (r - 2 * LX); }
+            else { lx = LX - 1; ly = 1 + (r - 2 * LX - TY); }
+        } else {
+            constexpr int BAND = RAD * LX;
+            if (r < 2 * BAND) {
+                const int k = r < BAND ? r : r - BAND;
+                ly = k / LX + (r < BAND ? 0 : LY - RAD);
+                lx = k % LX;
+            } else {
+                const int k = r - 2 * BAND;
+                const int side = k / (RAD * TY), m = k % (RAD * TY);
+                ly = RAD + m / RAD;
+                lx = (side ? LX - RAD : 0) + m % RAD;
+            }
+        }
     };
 
     for (int t = slot; t < ntiles; t += G) {
@@ -156,7 +173,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         if (has_ring) {
             ring_pos(tid, rlx, rly);
             int sx, sy;
-            rreal = map_pos<INOUT>(d, td.x0 + rlx - 1, td.y0 + rly - 1, sx, sy);
+            rreal = map_pos<INOUT>(d, td.x0 + rlx - RAD, td.y0 + rly - RAD, sx, sy);
             const Off ro = offs(sx, sy);
             if (rreal) {
 #pragma unroll
@@ -213,7 +230,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             int lx, ly;
             ring_pos(r, lx, ly);
             int sx, sy;
-            const bool real = map_pos<INOUT>(d, td.x0 + lx - 1, td.y0 + ly - 1, sx, sy);
+            const bool real = map_pos<INOUT>(d, td.x0 + lx - RAD, td.y0 + ly - RAD, sx, sy);
             const Off eo = offs(sx, sy);
             T raw[9], refs[NR];
             float pr = 0.f;
@@ -250,14 +267,29 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             }
             const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
 
-            // ---- E4 gradient (Table 1: 1/3 on axis neighbours, 1/12 on diagonals, no 1/cs^2), FP64
+            // ---- isotropic gradient (Sec. 3.1.1): sum over the stencil of w(|c|^2) phi(x + c) c with
+            // the Table 1 weights (E4: 1/3 on axis neighbours, 1/12 on diagonals; no 1/cs^2), or the
+            // central difference (E2: 1/2, 0), in FP64
             const double phi64 = s_phi[own];
             const float phi = (float)phi64;
             const double* P = s_phi + own;
             const double pE = P[1], pW = P[-1], pN = P[LX], pS = P[-LX];
             const double pNE = P[LX + 1], pNW = P[LX - 1], pSW = P[-LX - 1], pSE = P[-LX + 1];
-            const double gx64 = (1.0 / 3.0) * (pE - pW) + (1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
-            const double gy64 = (1.0 / 3.0) * (pN - pS) + (1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
+            double gx64 = d.gw[0] * (pE - pW) + d.gw[1] * ((pNE - pNW) + (pSE - pSW));
+            double gy64 = d.gw[0] * (pN - pS) + d.gw[1] * ((pNE + pNW) - (pSE + pSW));
+            if constexpr (RAD == 2) {
+                // E6 / E8: the layers |c|^2 = 4 (2, 0), 5 (2, 1) and (1, 2), and 8 (2, 2)
+                auto Q = [&](int i, int j) { return P[j * LX + i]; };
+                const double w4 = d.gw[2], w5 = d.gw[3], w8 = d.gw[4];
+                gx64 += 2.0 * w4 * (Q(2, 0) - Q(-2, 0)) +
+                        w5 * (2.0 * ((Q(2, 1) - Q(-2, 1)) + (Q(2, -1) - Q(-2, -1))) +
+                              ((Q(1, 2) - Q(-1, 2)) + (Q(1, -2) - Q(-1, -2)))) +
+                        2.0 * w8 * ((Q(2, 2) - Q(-2, 2)) + (Q(2, -2) - Q(-2, -2)));
+                gy64 += 2.0 * w4 * (Q(0, 2) - Q(0, -2)) +
+                        w5 * (2.0 * ((Q(1, 2) - Q(1, -2)) + (Q(-1, 2) - Q(-1, -2))) +
+                              ((Q(2, 1) - Q(2, -1)) + (Q(-2, 1) - Q(-2, -1)))) +
+                        2.0 * w8 * ((Q(2, 2) - Q(2, -2)) + (Q(-2, 2) - Q(-2, -2)));
+            }
             const bool has_normal = gx64 * gx64 + gy64 * gy64 > d.grad_eps2;
             const float gx = (float)gx64, gy = (float)gy64;
 
@@ -329,8 +361,9 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 for (int q = 0; q < 9; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
             }
 
-            // ---- vapour (Sec. 2.2.2): tau_g = 1/2 + (tau_vap - 1/2) clamp((1 - phi)/2, 0, 1)
-            const float sq = fminf(fmaxf(0.5f * (1.f - phi), 0.f), 1.f);
+            // ---- vapour (Sec. 2.2.2): tau_g = 1/2 + (tau_vap - 1/2) q with q = clamp((1 - phi)/2, 0, 1),
+            // or q = 1 in both phases for the symmetric (thermal) variant
+            const float sq = d.sym ? 1.f : fminf(fmaxf(0.5f * (1.f - phi), 0.f), 1.f);
             const float itg = 1.f / (0.5f + d.tauv_m_half * sq);
             const float srcg = d.half_Lsat * (phi - phip);
             float gs[5];
@@ -443,47 +476,54 @@ const char* tile_config_name(int i) { return (i >= 0 && i < kNumTiles) ? kTiles[
 int tile_config_tx(int i) { return kTiles[i].tx; }
 int tile_config_ty(int i) { return kTiles[i].ty; }
 
-template <int TX, int TY, class S, bool FLOW, bool INOUT>
+template <int TX, int TY, class S, bool FLOW, bool INOUT, int RAD>
 static void* step_fn() {
-    return reinterpret_cast<void*>(&k_step<TX, TY, S, FLOW, INOUT>);
+    return reinterpret_cast<void*>(&k_step<TX, TY, S, FLOW, INOUT, RAD>);
 }
 
-template <class S, bool FLOW, bool INOUT>
+template <class S, bool FLOW, bool INOUT, int RAD>
 static void* step_fn_tile(int cfg) {
     switch (cfg) {
-        case 0: return step_fn<64, 4, S, FLOW, INOUT>();
-        case 1: return step_fn<64, 8, S, FLOW, INOUT>();
-        case 2: return step_fn<128, 2, S, FLOW, INOUT>();
-        case 3: return step_fn<128, 4, S, FLOW, INOUT>();
-        case 4: return step_fn<64, 2, S, FLOW, INOUT>();
-        case 5: return step_fn<32, 8, S, FLOW, INOUT>();
+        case 0: return step_fn<64, 4, S, FLOW, INOUT, RAD>();
+        case 1: return step_fn<64, 8, S, FLOW, INOUT, RAD>();
+        case 2: return step_fn<128, 2, S, FLOW, INOUT, RAD>();
+        case 3: return step_fn<128, 4, S, FLOW, INOUT, RAD>();
+        case 4: return step_fn<64, 2, S, FLOW, INOUT, RAD>();
+        case 5: return step_fn<32, 8, S, FLOW, INOUT, RAD>();
     }
     return nullptr;
 }
 
-template <class S>
+template <class S, int RAD>
 static void* step_fn_store(int cfg, int flow, int inout) {
-    if (!flow) return step_fn_tile<S, false, false>(cfg);
-    if (!inout) return step_fn_tile<S, true, false>(cfg);
-    return step_fn_tile<S, true, true>(cfg);
+    if (!flow) return step_fn_tile<S, false, false, RAD>(cfg);
+    if (!inout) return step_fn_tile<S, true, false, RAD>(cfg);
+    return step_fn_tile<S, true, true, RAD>(cfg);
 }
 
-static void* step_kernel(int cfg, int storage, int flow, int inout) {
+template <int RAD>
+static void* step_kernel_rad(int cfg, int storage, int flow, int inout) {
+    switch (storage) {
+        case 0: return step_fn_store<StoreF32, RAD>(cfg, flow, inout);
+        case 1: return step_fn_store<StoreF16, RAD>(cfg, flow, inout);
+        case 2: return step_fn_store<StoreBF16, RAD>(cfg, flow, inout);
+    }
+    return nullptr;
+}
+
+static void* step_kernel(int cfg, int storage, int flow, int inout, int rad) {
     if (cfg < 0 || cfg >= kNumTiles) return nullptr;
     if (inout && !flow) return nullptr;
-    switch (storage) {
-        case 0: return step_fn_store<StoreF32>(cfg, flow, inout);
-        case 1: return step_fn_store<StoreF16>(cfg, flow, inout);
-        case 2: return step_fn_store<StoreBF16>(cfg, flow, inout);
-    }
+    if (rad == 1) return step_kernel_rad<1>(cfg, storage, flow, inout);
+    if (rad == 2) return step_kernel_rad<2>(cfg, storage, flow, inout);
     return nullptr;
 }
 
 // Grid of a step launch.  grid_mode 0: one workgroup per tile, dispatched in (XCD-contiguous) tile
 // order -- measured best for streaming traffic on MI355X.  grid_mode 1: a persistent grid of one
 // wave of resident workgroups that loops over the tiles.
-int step_grid(int cfg, int ntiles, int storage, int flow, int inout, int grid_mode) {
-    void* fn = step_kernel(cfg, storage, flow, inout);
+int step_grid(int cfg, int ntiles, int storage, int flow, int inout, int rad, int grid_mode) {
+    void* fn = step_kernel(cfg, storage, flow, inout, rad);
     if (!fn || ntiles <= 0) return 0;
     if (grid_mode == 0) return ntiles;
     int per_cu = 0;
@@ -501,9 +541,9 @@ int step_grid(int cfg, int ntiles, int storage, int flow, int inout, int grid_mo
     return (int)(g > 0 ? g : ntiles);
 }
 
-hipError_t launch_step(int cfg, int storage, int flow, int inout, const DomDesc* doms_dev,
+hipError_t launch_step(int cfg, int storage, int flow, int inout, int rad, const DomDesc* doms_dev,
                        const TileDesc* tiles_dev, int ntiles, int grid, int par, hipStream_t s) {
-    void* fn = step_kernel(cfg, storage, flow, inout);
+    void* fn = step_kernel(cfg, storage, flow, inout, rad);
     if (!fn) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
     const int nt = kTiles[cfg].tx * kTiles[cfg].ty;

@@ -42,6 +42,7 @@ class snowlb_params(ctypes.Structure):
         ("grad_eps2", ctypes.c_double), ("U0", ctypes.c_double),
         ("seed_x", ctypes.c_double), ("seed_y", ctypes.c_double), ("seed_r", ctypes.c_double),
         ("init_width", ctypes.c_double), ("diag_every", ctypes.c_int32), ("tile", ctypes.c_int32),
+        ("stencil", ctypes.c_int32), ("symmetric", ctypes.c_int32),
     ]
 
 
@@ -301,6 +302,8 @@ def make_params(cfg: dict, storage: str | int = "fp32", tile: int = 0, diag_ever
     p.bc_x = int(cfg.get("inout", 0))
     p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
     p.n_fold = int(cfg.get("n_fold", 6))
+    p.stencil = int(cfg.get("stencil", 4))
+    p.symmetric = int(cfg.get("symmetric", 0))
     for k in ("eps", "W0", "tau0", "lam", "L_sat", "tau_vap", "tau_f", "h_drag", "kappa_N", "rho0",
               "u_in", "U_in", "grad_eps2", "U0"):
         if k in cfg:

@@ -50,6 +50,16 @@ C5 = _cfg(name="c5_adjoint_512", nx=512, ny=512, flow=0, inout=0, seed=(256.0, 2
 C5["eps"] = C5["eps_start"]
 C5["U0"] = C5["U0_start"]
 
+# Stencil study of Sec. 3.1.1 in lattice units: a hexagonal crystal grown by the symmetric thermal
+# model on 800^2 with dx = 0.01, dt = 1.5e-5, i.e. W0 = 0.0125/dx = 1.25, tau0 = 1.5625e-4/dt,
+# kappa = 1 -> D = kappa dt/dx^2 = 0.15 (tau_vap = 1/2 + 3 D = 0.95, so W0^2/tau0 = D), lambda = 10,
+# eps = 0.05, undercooling Delta = 0.3, seed R = 10 at (400, 400), 1e5 steps.  The reduced
+# temperature u enters as U = -u (undercooling U0 = Delta) with latent heat L_sat = 1 and the
+# diffusivity q = 1 in both phases.  Set "stencil" to 2, 4, 6 or 8.
+F1 = _cfg(name="f1_stencil_study_800", nx=800, ny=800, flow=0, inout=0, W0=1.25, tau0=1.5625e-4 / 1.5e-5,
+          tau_vap=0.95, lam=10.0, eps=0.05, L_sat=1.0, U0=0.3, symmetric=1, stencil=4,
+          seed=(400.0, 400.0, 10.0), w_init=1.25, steps=100000)
+
 SIDES = (256, 384, 512, 768, 1024)
 
 

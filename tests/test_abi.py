@@ -36,6 +36,7 @@ def test_defaults_are_valid():
     p = S.snowlb_params_default()
     assert S.snowlb_validate(p) == (0, "")
     assert (p.nx, p.ny, p.n_fold) == (128, 128, 6)
+    assert (p.stencil, p.symmetric) == (4, 0)
 
 
 @pytest.mark.parametrize("field,value,frag", [
@@ -43,6 +44,7 @@ def test_defaults_are_valid():
     ("n_fold", 5, "n_fold"), ("storage", 3, "storage"), ("eps", 0.6, "eps"),
     ("W0", 0.0, "W0"), ("tile", 99, "tile"), ("diag_every", -1, "diag_every"),
     ("eps", float("nan"), "non-finite"), ("init_width", 0.0, "init_width"),
+    ("stencil", 3, "stencil"), ("stencil", 0, "stencil"), ("symmetric", 2, "symmetric"),
 ])
 def test_invalid_params_rejected_before_gpu(field, value, frag):
     p = S.snowlb_params_default()
@@ -97,6 +99,13 @@ def test_batch_rejects_mixed_kernels_before_gpu():
     assert S.lib().snowlb_batch_create(arr, 2, ctypes.byref(out)) == S.EINVAL
     assert "domain 0" in S.lib().snowlb_batch_last_error(None).decode()
     assert S.lib().snowlb_batch_create(arr, 0, ctypes.byref(out)) == S.EINVAL
+    # E2 and E4 share a kernel (one-cell halo); E4 and E8 do not
+    a = S.snowlb_params_default()
+    b = S.snowlb_params_default()
+    b.stencil = 8
+    arr = (S.snowlb_params * 2)(a, b)
+    assert S.lib().snowlb_batch_create(arr, 2, ctypes.byref(out)) == S.EINVAL and not out.value
+    assert "stencil" in S.lib().snowlb_batch_last_error(None).decode()
 
 
 def test_lattice_size_limit():

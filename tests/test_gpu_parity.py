@@ -55,11 +55,12 @@ def report(name, err):
     print("  %-28s max abs err %.3e" % (name, err), flush=True)
 
 
+@pytest.mark.parametrize("stencil", [4, 2, 6, 8])
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("shape", [(70, 37), (128, 64)])
-def test_one_step_from_random_state(case, shape):
+def test_one_step_from_random_state(case, shape, stencil):
     nx, ny = shape
-    cfg = cfg_of(nx, ny, **CASES[case])
+    cfg = cfg_of(nx, ny, stencil=stencil, **CASES[case])
     st = W.random_state(nx, ny, seed=nx * 1000 + ny, flow=bool(cfg["flow"]))
     o, sim = load_both(cfg, st)
     o.step(1)
@@ -68,15 +69,33 @@ def test_one_step_from_random_state(case, shape):
     got = gpu_state(sim, cfg["flow"])
     for k in got:
         err = np.abs(got[k] - want[k]).max()
-        report("%s %s %s" % (case, shape, k), err)
+        report("E%d %s %s %s" % (stencil, case, shape, k), err)
         assert err < 2e-6, k
 
 
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_step_symmetric_diffusivity(case):
+    """The symmetric (thermal) variant, q = 1 in both phases, with the two-cell E6 stencil."""
+    nx, ny = 70, 37
+    cfg = cfg_of(nx, ny, stencil=6, symmetric=1, **CASES[case])
+    st = W.random_state(nx, ny, seed=99, flow=bool(cfg["flow"]))
+    o, sim = load_both(cfg, st)
+    o.step(1)
+    sim.step(1)
+    want = o.get_state()
+    got = gpu_state(sim, cfg["flow"])
+    for k in got:
+        err = np.abs(got[k] - want[k]).max()
+        report("symmetric %s %s" % (case, k), err)
+        assert err < 2e-6, k
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_tile_configurations_bitwise_identical(case, storage):
+def test_tile_configurations_bitwise_identical(case, storage, stencil):
     nx, ny = 131, 53  # ragged in both directions for every tile shape
-    cfg = cfg_of(nx, ny, **CASES[case])
+    cfg = cfg_of(nx, ny, stencil=stencil, **CASES[case])
     st = {k: torch.from_numpy(f32(v)) for k, v in W.random_state(nx, ny, seed=5, flow=bool(cfg["flow"])).items()}
     ref = None
     for t in range(S.snowlb_tile_count()):
@@ -327,16 +346,17 @@ def source_refs(qs, cfg):
     return refs
 
 
+@pytest.mark.parametrize("stencil", [4, 8])
 @pytest.mark.parametrize("storage", ["fp16", "bf16"])
 @pytest.mark.parametrize("case", list(CASES))
-def test_half_storage_one_step(case, storage):
+def test_half_storage_one_step(case, storage, stencil):
     """One step from an arbitrary state held in 16-bit storage.  Both sides start from the same
     quantized state (rounded here, by the documented encoding); the GPU's output is then rounded once
     more, so each population may differ from the oracle's by half a unit in the last place of its
     deviation d = p/w - m (m: phi(t) of the holding cell for h; U, resp. rho + 3 c.j, of the source
     cell for g, resp. f), plus FP32 arithmetic and the rounding of the references."""
     nx, ny = 96, 40
-    cfg = cfg_of(nx, ny, **CASES[case])
+    cfg = cfg_of(nx, ny, stencil=stencil, **CASES[case])
     st = {k: f32(v) for k, v in W.random_state(nx, ny, seed=77, flow=bool(cfg["flow"]),
                                                  well_conditioned=True).items()}
     qs = quantize_written_state(st, storage, cfg)

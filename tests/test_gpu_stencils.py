@@ -1,0 +1,111 @@
+"""GPU parity of the gradient-stencil family and the symmetric (thermal) variant of the Sec. 3.1.1
+study: multi-step runs of the HIP step (through the C ABI) against the FP64 oracle.
+
+Bars as for the E4 path: phase field and supersaturation within 1e-4 of the oracle over the run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_07163_amd import snowlb as S
+from paper_2101_07163_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def report(name, err):
+    print("  %-34s max abs err %.3e" % (name, err), flush=True)
+
+
+def run_both(cfg, checkpoints, fields=("phi", "U")):
+    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
+    sim = S.Sim(cfg).init()
+    errs = []
+    for t in checkpoints:
+        o.step(t - o.step_count)
+        sim.step(t - sim.step_count)
+        F = o.fields()
+        e = {k: float(np.abs(sim.read(k).double().cpu().numpy() - F[k]).max()) for k in fields}
+        errs.append((t, e))
+    phi = sim.read("phi").double().cpu().numpy()
+    return errs, phi, o
+
+
+@pytest.mark.parametrize("stencil", [2, 6, 8])
+def test_stencil_c1_plain_128_run(stencil):
+    """The 128^2 plain workload over its 2000 steps with the E2, E6 and E8 gradients."""
+    cfg = dict(W.C1, stencil=stencil)
+    errs, phi, o = run_both(cfg, (500, 2000))
+    for t, e in errs:
+        for k, v in e.items():
+            report("E%d C1 step %d %s" % (stencil, t, k), v)
+            assert v <= 1e-4, (t, k)
+    assert int((phi > 0).sum()) == int(o.diag()["n_solid"])
+
+
+@pytest.mark.parametrize("stencil", [2, 8])
+def test_stencil_ventilated_small_run(stencil):
+    """Ventilated crystal on 160 x 96 (inlet ghost phi = -1 and outlet copy two cells deep for E8)."""
+    cfg = dict(W.COMMON, nx=160, ny=96, flow=1, inout=1, u_in=0.02, U_in=0.6, U0=0.6, seed=(50.0, 48.0, 8.0),
+               w_init=1.0, stencil=stencil)
+    errs, _, _ = run_both(cfg, (400,), fields=("phi", "U", "rho", "ux", "uy"))
+    for t, e in errs:
+        for k, v in e.items():
+            report("E%d ventilated %s" % (stencil, k), v)
+            assert v <= 1e-4, k
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
+def test_symmetric_thermal_small_run(stencil):
+    """The thermal stencil-study model (q = 1, lambda = 10, U0 = 0.3, W0 = 1.25) on 160^2, 2000 steps."""
+    cfg = dict(W.F1, nx=160, ny=160, seed=(80.0, 80.0, 10.0), stencil=stencil)
+    errs, _, _ = run_both(cfg, (500, 2000))
+    for t, e in errs:
+        for k, v in e.items():
+            report("E%d thermal step %d %s" % (stencil, t, k), v)
+            assert v <= 1e-4, (t, k)
+
+
+def _radius(phi, cx, cy, theta, ds=0.05):
+    """Distance from (cx, cy) to the outermost phi = 0 crossing along the ray at angle theta
+    (bilinear interpolation of phi, linear interpolation of the crossing)."""
+    n = phi.shape[0]
+    s = np.arange(0.0, n / 2 - 1, ds)
+    x, y = cx + s * np.cos(theta), cy + s * np.sin(theta)
+    x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
+    fx, fy = x - x0, y - y0
+    v = (phi[y0 % n, x0 % n] * (1 - fx) * (1 - fy) + phi[y0 % n, (x0 + 1) % n] * fx * (1 - fy) +
+         phi[(y0 + 1) % n, x0 % n] * (1 - fx) * fy + phi[(y0 + 1) % n, (x0 + 1) % n] * fx * fy)
+    i = np.nonzero(v >= 0)[0][-1]
+    return s[i] + ds * v[i] / (v[i] - v[i + 1])
+
+
+def test_stencil_study_orientation_artifact():
+    """The stencil study of Sec. 3.1.1 at its own size (800^2, 1e5 steps, thermal model): the six
+    tips of the hexagonal crystal grow along 0, 60, ..., 300 degrees.  With the central difference
+    (E2) the tips on the lattice axis and those at 60 degrees differ in length (the gradient's error
+    term depends on the axes); with the isotropic E4, E6 and E8 stencils the difference is at least
+    ten times smaller.  The lattice's own mirror symmetries hold for every stencil: the four tips at
+    60, 120, 240 and 300 degrees are equal, and so are those at 0 and 180 degrees (to rounding)."""
+    spread = {}
+    for stencil in (2, 4, 6, 8):
+        cfg = dict(W.F1, stencil=stencil)
+        sim = S.Sim(cfg).init()
+        sim.step(cfg["steps"])
+        phi = sim.read("phi").double().cpu().numpy()
+        cx, cy = cfg["seed"][:2]
+        r = [_radius(phi, cx, cy, np.radians(a)) for a in (0, 60, 120, 180, 240, 300)]
+        # mirror images agree up to FP32 rounding (the stencil sums run in one fixed order, which is
+        # not mirror symmetric) amplified by 1e5 steps of growth: 1e-3 cells here, against the 3.6
+        # cells of E2's orientation artifact
+        assert max(r[1], r[2], r[4], r[5]) - min(r[1], r[2], r[4], r[5]) < 1e-2
+        assert abs(r[0] - r[3]) < 1e-2
+        assert 100 < np.mean(r) < 300   # the tips have grown far from the seed (R = 10) and stay inside
+        spread[stencil] = abs(r[0] - r[1]) / np.mean(r)
+        print("  E%d tips %s  spread %.2e" % (stencil, " ".join("%.2f" % v for v in r), spread[stencil]),
+              flush=True)
+    assert spread[2] > 1e-2
+    for stencil in (4, 6, 8):
+        assert spread[stencil] < 0.1 * spread[2], stencil
