@@ -129,6 +129,24 @@ def stencil_family(S, torch, W, cfg, storage, steps, tile):
     return res
 
 
+def habit_sweep(S, torch, W, steps=20000, warmup=200):
+    """The seven Table 2 morphologies (Sec. 3.2.1) on 400^2 through the physical-unit front end, as
+    one batch: aggregate MLUPS."""
+    from paper_2101_07163_amd import units
+    cfgs = [units.plate_regime(U0, L) for (_, _, U0, L) in W.TABLE2]
+    b = S.Batch(cfgs, tile=-1).init()
+    b.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res = {"domains": len(cfgs), "cells": b.cells, "steps": steps, "tile": S.snowlb_tile_name(b.tile),
+           "batched_MLUPS": round(b.cells * steps / wall / 1e6, 1)}
+    del b
+    return res
+
+
 def batch_sweep(S, torch, W, steps=200, warmup=20, solo_steps=64):
     """The 64-crystal sweep as one batch (one launch per step over all tiles) against the same work
     done crystal by crystal (solo contexts, graph-replayed), both in aggregate MLUPS."""
@@ -234,7 +252,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5,stencils",
+    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5,stencils,table2",
                     help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16, "
                          "c4 (64-crystal batch), c5 (adjoint/forward time ratio)")
     args = ap.parse_args()
@@ -315,6 +333,9 @@ def main():
         if "stencils" in wanted:
             extras["stencils"] = stencil_family(S, torch, W, cfg, args.storage, min(args.steps, 1000), args.tile)
             log("gradient stencils: %s" % extras["stencils"])
+        if "table2" in wanted:
+            extras["table2_habits"] = habit_sweep(S, torch, W)
+            log("Table 2 habit sweep: %s" % extras["table2_habits"])
         if "c4" in wanted:
             extras["c4_batch"] = batch_sweep(S, torch, W)
             log("64-crystal batch: %s" % extras["c4_batch"])

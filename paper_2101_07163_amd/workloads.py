@@ -60,6 +60,18 @@ F1 = _cfg(name="f1_stencil_study_800", nx=800, ny=800, flow=0, inout=0, W0=1.25,
           tau_vap=0.95, lam=10.0, eps=0.05, L_sat=1.0, U0=0.3, symmetric=1, stencil=4,
           seed=(400.0, 400.0, 10.0), w_init=1.25, steps=100000)
 
+# Table 2 (Sec. 3.2.1): the seven plate-regime morphologies, (number, name, U0, L_sat).  The lattice
+# set-up of each row is units.plate_regime(U0, L_sat).
+TABLE2 = (
+    (1, "solid plate", 0.4, 2.0),
+    (2, "stellar plate I", 0.5, 1.8),
+    (3, "sectored plate", 0.5, 1.6),
+    (4, "stars", 0.6, 1.0),
+    (5, "fern dendrite", 0.8, 1.6),
+    (6, "fernlike stellar", 0.7, 1.6),
+    (7, "stellar plate II", 0.5, 1.2),
+)
+
 SIDES = (256, 384, 512, 768, 1024)
 
 

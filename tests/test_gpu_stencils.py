@@ -9,6 +9,7 @@ import pytest
 import oracle
 from paper_2101_07163_amd import snowlb as S
 from paper_2101_07163_amd import workloads as W
+from shapes import ray_radius
 
 pytestmark = pytest.mark.gpu
 
@@ -68,20 +69,6 @@ def test_symmetric_thermal_small_run(stencil):
             assert v <= 1e-4, (t, k)
 
 
-def _radius(phi, cx, cy, theta, ds=0.05):
-    """Distance from (cx, cy) to the outermost phi = 0 crossing along the ray at angle theta
-    (bilinear interpolation of phi, linear interpolation of the crossing)."""
-    n = phi.shape[0]
-    s = np.arange(0.0, n / 2 - 1, ds)
-    x, y = cx + s * np.cos(theta), cy + s * np.sin(theta)
-    x0, y0 = np.floor(x).astype(int), np.floor(y).astype(int)
-    fx, fy = x - x0, y - y0
-    v = (phi[y0 % n, x0 % n] * (1 - fx) * (1 - fy) + phi[y0 % n, (x0 + 1) % n] * fx * (1 - fy) +
-         phi[(y0 + 1) % n, x0 % n] * (1 - fx) * fy + phi[(y0 + 1) % n, (x0 + 1) % n] * fx * fy)
-    i = np.nonzero(v >= 0)[0][-1]
-    return s[i] + ds * v[i] / (v[i] - v[i + 1])
-
-
 def test_stencil_study_orientation_artifact():
     """The stencil study of Sec. 3.1.1 at its own size (800^2, 1e5 steps, thermal model): the six
     tips of the hexagonal crystal grow along 0, 60, ..., 300 degrees.  With the central difference
@@ -96,7 +83,7 @@ def test_stencil_study_orientation_artifact():
         sim.step(cfg["steps"])
         phi = sim.read("phi").double().cpu().numpy()
         cx, cy = cfg["seed"][:2]
-        r = [_radius(phi, cx, cy, np.radians(a)) for a in (0, 60, 120, 180, 240, 300)]
+        r = [ray_radius(phi, cx, cy, np.radians(a)) for a in (0, 60, 120, 180, 240, 300)]
         # mirror images agree up to FP32 rounding (the stencil sums run in one fixed order, which is
         # not mirror symmetric) amplified by 1e5 steps of growth: 1e-3 cells here, against the 3.6
         # cells of E2's orientation artifact
