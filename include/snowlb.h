@@ -30,6 +30,9 @@
  *                          buffers a tile touches start on different HBM channels (default 2304)
  *   SNOWLB_GRAPH_STEPS     steps per captured graph of snowlb_step (default 32, even)
  *   SNOWLB_NO_GRAPH        1: launch every step directly instead of replaying graphs
+ *   SNOWLB_ADJ_OVERLAP     0: run the adjoint backward pass in serial order on the caller's stream
+ *                          (default 1: recompute the next checkpoint interval on a second stream of
+ *                          the context while the current one is reversed; bitwise the same results)
  */
 #ifndef SNOWLB_H
 #define SNOWLB_H
@@ -193,8 +196,10 @@ int32_t snowlb_get_grid_mode(const snowlb_ctx* ctx);
  * (ny x nx device field) for any loss L(phi_T) and returns, by the hand-written reverse of each step
  * with the states recomputed from the checkpoints: dL/dU_init (ny x nx device field, the gradient
  * with respect to the initial supersaturation field), dL/deps and dL/dU0 = sum dL/dU_init (host
- * doubles, reduced in FP64 in a fixed order).  Memory: about (n/stride + stride) state copies.
- * The backward may be called several times after one forward (different dL/dphi_T). */
+ * doubles, reduced in FP64 in a fixed order).  Memory: about (n/stride + 2 stride) state copies.
+ * The backward may be called several times after one forward (different dL/dphi_T).  It recomputes
+ * checkpoint intervals on a second stream that the context owns (see SNOWLB_ADJ_OVERLAP), ordered
+ * after all work queued on `stream` before the call; it returns when the work of both is done. */
 snowlb_status snowlb_adj_forward(snowlb_ctx* ctx, int32_t n_steps, int32_t ckpt_stride, void* stream);
 snowlb_status snowlb_adj_backward(snowlb_ctx* ctx, const float* dL_dphiT_dev, float* dL_dUinit_dev,
                                   double* dL_deps_host, double* dL_dU0_host, void* stream);

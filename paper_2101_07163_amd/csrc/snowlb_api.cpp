@@ -382,8 +382,12 @@ struct snowlb_ctx {
         double* rows = nullptr;
         double* d_out = nullptr;
         double* h_out = nullptr;  // pinned, 2 doubles
-        DomDesc* d_segdoms = nullptr;
+        DomDesc* d_segdoms = nullptr;  // two segment areas of (stride - 1) step descriptors each
         int nsegdoms = 0;
+        // the backward pass recomputes the next interval on its own stream while the current one is
+        // reversed; events order the two (index: segment area)
+        hipStream_t rstream = nullptr;
+        hipEvent_t ev_start = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_rev[2] = {nullptr, nullptr};
         // captured segment programs (the recompute and reverse steps of one checkpoint interval),
         // each keyed by every value its kernel arguments bake in
         struct SegGraph {
@@ -528,6 +532,13 @@ void adj_free(snowlb_ctx* c) {
     c->adj.buf = nullptr;
     c->adj.epart = c->adj.rows = c->adj.d_out = c->adj.h_out = nullptr;
     c->adj.d_segdoms = nullptr;
+    for (hipEvent_t* e : {&c->adj.ev_start, &c->adj.ev_rec[0], &c->adj.ev_rec[1], &c->adj.ev_rev[0], &c->adj.ev_rev[1]})
+        if (*e) {
+            (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    if (c->adj.rstream) (void)hipStreamDestroy(c->adj.rstream);
+    c->adj.rstream = nullptr;
     c->adj.nslots = 0;
     c->adj.nsegdoms = 0;
     c->adj.have_forward = false;
@@ -894,7 +905,7 @@ snowlb_status snowlb_adj_forward(snowlb_ctx* c, int32_t n, int32_t stride, void*
     const int st = stride > 0 ? stride : (int)std::ceil(std::sqrt((double)n));
     const int nck = (n + st - 1) / st;
     const int64_t slot_bytes = c->pop_bytes + c->phip_bytes;
-    const int64_t need = (int64_t)nck + st;
+    const int64_t need = (int64_t)nck + 2 * (int64_t)st;  // checkpoints, then two segment areas
     if (c->adj.nslots < need || c->adj.slot_bytes != slot_bytes) {
         if (c->adj.slots) (void)hipFree(c->adj.slots);
         c->adj.slots = nullptr;
@@ -919,11 +930,15 @@ snowlb_status snowlb_adj_forward(snowlb_ctx* c, int32_t n, int32_t stride, void*
     return SNOWLB_OK;
 }
 
-// The captured program of one checkpoint interval of length len whose reverse steps start reading
-// lambda[cur]: (len - 1) recompute steps through the segment descriptors, then len reverse steps.
-// Programs are cached on the context, keyed by every value their kernel arguments bake in.
-static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const lam[2], int len, int cur, int grid,
-                                       hipGraphExec_t* out) {
+// First slot of segment area a (two areas of `stride` states follow the checkpoints).
+static int64_t adj_area_slot(const snowlb_ctx* c, int a) { return (int64_t)c->adj.nck + (int64_t)a * c->adj.stride; }
+
+// Captured programs of one checkpoint interval of length len in segment area `area`: kind 0, the
+// (len - 1) recompute steps from the checkpoint copied into the area's first slot; kind 1, the len
+// reverse steps over the area's states, starting from lambda[cur].  Programs are cached on the
+// context, keyed by every value their kernel arguments bake in.
+static snowlb_status adj_graph(snowlb_ctx* c, int kind, AdjDesc A, float* const lam[2], int area, int len, int cur,
+                               int grid, hipGraphExec_t* out) {
     Driver& D = c->drv;
     struct Key {
         AdjDesc A;
@@ -933,45 +948,54 @@ static snowlb_status adj_segment_graph(snowlb_ctx* c, AdjDesc A, float* const la
         const void* segdoms;
         const void* tiles;
         int64_t slot_bytes;
-        int32_t nck, tile, grid, storage, len, cur;
+        int32_t nck, stride, tile, grid, storage, len, cur, kind, area, pad;
     } key;
     std::memset(&key, 0, sizeof key);
-    key.A = A;
-    key.A.st = key.A.lin = key.A.lppin = nullptr;
-    key.A.lout = key.A.lppout = nullptr;
-    key.lam0 = lam[0];
-    key.lam1 = lam[1];
+    if (kind == 1) {
+        key.A = A;
+        key.A.st = key.A.lin = key.A.lppin = nullptr;
+        key.A.lout = key.A.lppout = nullptr;
+        key.lam0 = lam[0];
+        key.lam1 = lam[1];
+        key.cur = cur;
+    } else {
+        key.segdoms = c->adj.d_segdoms;
+        key.tiles = D.d_tiles[D.tile];
+        key.tile = D.tile;
+        key.grid = grid;
+        key.storage = c->p.storage;
+    }
     key.slots = c->adj.slots;
-    key.segdoms = c->adj.d_segdoms;
-    key.tiles = D.d_tiles[D.tile];
     key.slot_bytes = c->adj.slot_bytes;
     key.nck = c->adj.nck;
-    key.tile = D.tile;
-    key.grid = grid;
-    key.storage = c->p.storage;
+    key.stride = c->adj.stride;
     key.len = len;
-    key.cur = cur;
+    key.kind = kind;
+    key.area = area;
     const char* kb = reinterpret_cast<const char*>(&key);
     for (auto& sg : c->adj.graphs)
         if (sg.key.size() == sizeof key && std::memcmp(sg.key.data(), kb, sizeof key) == 0) {
             *out = sg.exec;
             return SNOWLB_OK;
         }
-    if (c->adj.graphs.size() >= 8) adj_drop_graphs(c);
     hipStream_t cs = D.cap_stream;
     HIPCHK(c, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
-    for (int i = 0; i + 1 < len && le == hipSuccess; ++i)
-        le = launch_step(D.tile, c->p.storage, 0, 0, 1, c->adj.d_segdoms + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid,
-                         0, cs);
-    for (int i = len - 1; i >= 0 && le == hipSuccess; --i) {
-        A.st = (const float*)adj_slot(c, c->adj.nck + i);
-        A.lin = lam[cur];
-        A.lout = lam[1 - cur];
-        A.lppin = lam[cur] + kAdjPlanes * adj_cells(c);
-        A.lppout = lam[1 - cur] + kAdjPlanes * adj_cells(c);
-        le = launch_adj_step(A, cs);
-        cur ^= 1;
+    if (kind == 0) {
+        const DomDesc* sd = c->adj.d_segdoms + (int64_t)area * std::max(c->adj.stride - 1, 1);
+        for (int i = 0; i + 1 < len && le == hipSuccess; ++i)
+            le = launch_step(D.tile, c->p.storage, 0, 0, 1, sd + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid, 0, cs);
+    } else {
+        const int64_t base = adj_area_slot(c, area);
+        for (int i = len - 1; i >= 0 && le == hipSuccess; --i) {
+            A.st = (const float*)adj_slot(c, base + i);
+            A.lin = lam[cur];
+            A.lout = lam[1 - cur];
+            A.lppin = lam[cur] + kAdjPlanes * adj_cells(c);
+            A.lppout = lam[1 - cur] + kAdjPlanes * adj_cells(c);
+            le = launch_adj_step(A, cs);
+            cur ^= 1;
+        }
     }
     hipGraph_t g = nullptr;
     const hipError_t ee = hipStreamEndCapture(cs, &g);
@@ -996,6 +1020,10 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     if (!dphi || !dU || !deps || !dU0) return fail(c, SNOWLB_EINVAL, "NULL argument");
     if (!c->adj.have_forward) return fail(c, SNOWLB_ESTATE, "adjoint backward before adjoint forward");
     hipStream_t s = (hipStream_t)stream;
+    // One backward pass uses at most 12 programs (recompute: 2 areas x 2 interval lengths; reverse: 2
+    // areas x 2 lambda parities x 2 lengths).  Programs are only dropped here, while none can be in
+    // flight: the previous pass synchronised its stream before returning.
+    if (c->adj.graphs.size() > 4) adj_drop_graphs(c);
     // lambda buffers: the 14 planes of g and h in the populations' cell order, then phi_prev's plane
     const int64_t cells = adj_cells(c);
     AdjDesc A{};
@@ -1020,16 +1048,20 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
         HIPCHK(c, hipHostMalloc(&c->adj.h_out, 2 * sizeof(double), hipHostMallocDefault));
     }
     const int st = c->adj.stride, n = c->adj.n;
-    if (c->adj.nsegdoms != std::max(st - 1, 1)) {
-        std::vector<DomDesc> h((size_t)std::max(st - 1, 1), c->dom);
-        for (int i = 0; i + 1 < st; ++i) {
-            char* a = adj_slot(c, c->adj.nck + i);
-            char* b = adj_slot(c, c->adj.nck + i + 1);
-            h[i].pop[0] = a;
-            h[i].pop[1] = b;
-            h[i].phip[0] = (float*)(a + c->pop_bytes);
-            h[i].phip[1] = (float*)(b + c->pop_bytes);
-        }
+    const int per_area = std::max(st - 1, 1);
+    if (c->adj.nsegdoms != 2 * per_area) {
+        // step i of a recompute in area `ar` reads slot i of the area and writes slot i + 1
+        std::vector<DomDesc> h((size_t)(2 * per_area), c->dom);
+        for (int ar = 0; ar < 2; ++ar)
+            for (int i = 0; i + 1 < st; ++i) {
+                DomDesc& d = h[(size_t)(ar * per_area + i)];
+                char* a = adj_slot(c, adj_area_slot(c, ar) + i);
+                char* b = adj_slot(c, adj_area_slot(c, ar) + i + 1);
+                d.pop[0] = a;
+                d.pop[1] = b;
+                d.phip[0] = (float*)(a + c->pop_bytes);
+                d.phip[1] = (float*)(b + c->pop_bytes);
+            }
         if (c->adj.d_segdoms) (void)hipFree(c->adj.d_segdoms);
         c->adj.d_segdoms = nullptr;
         HIPCHK(c, hipMalloc(&c->adj.d_segdoms, h.size() * sizeof(DomDesc)));
@@ -1047,18 +1079,52 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     snowlb_status r = from_driver(c, D.ensure_tiles(D.tile));
     if (r) return r;
     const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, 1, D.grid_mode);
-    // Each checkpoint interval: copy its checkpoint into the first segment slot, then replay the
-    // captured program of (len - 1) recompute steps and len reverse steps.  At most three distinct
-    // programs occur (the shorter last interval, and a full one for each parity of lambda).
+    // Checkpoint intervals are reversed from the last to the first.  Interval k lives in segment area
+    // k % 2: its checkpoint is copied into the area's first slot, (len - 1) recompute steps fill the
+    // rest, and len reverse steps consume it.  With overlap (the default), interval k - 1 is
+    // recomputed on the context's second stream while interval k is reversed on the caller's: the
+    // recompute waits for the reverse of interval k + 1 (the last user of its area), and each reverse
+    // waits for its own recompute.  Every kernel sees the same inputs as in the serial order, so the
+    // results are bitwise the same.
+    const bool overlap = env_int("SNOWLB_ADJ_OVERLAP", 1) != 0;
+    if (overlap && !c->adj.rstream) {
+        HIPCHK(c, hipStreamCreateWithFlags(&c->adj.rstream, hipStreamNonBlocking));
+        for (hipEvent_t* ev : {&c->adj.ev_start, &c->adj.ev_rec[0], &c->adj.ev_rec[1], &c->adj.ev_rev[0],
+                               &c->adj.ev_rev[1]})
+            HIPCHK(c, hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    }
+    hipStream_t rs = overlap ? c->adj.rstream : s;
+    auto recompute = [&](int k) -> snowlb_status {
+        const int len = std::min(st, n - k * st), ar = k & 1;
+        HIPCHK(c, hipMemcpyAsync(adj_slot(c, adj_area_slot(c, ar)), adj_slot(c, k), (size_t)c->adj.slot_bytes,
+                                 hipMemcpyDeviceToDevice, rs));
+        if (len > 1) {
+            hipGraphExec_t g = nullptr;
+            if (snowlb_status r2 = adj_graph(c, 0, A, lam, ar, len, 0, grid, &g)) return r2;
+            HIPCHK(c, hipGraphLaunch(g, rs));
+        }
+        if (overlap) HIPCHK(c, hipEventRecord(c->adj.ev_rec[ar], rs));
+        return SNOWLB_OK;
+    };
+    if (overlap) {  // the second stream starts after everything queued on the caller's stream so far
+        HIPCHK(c, hipEventRecord(c->adj.ev_start, s));
+        HIPCHK(c, hipStreamWaitEvent(rs, c->adj.ev_start, 0));
+    }
+    if (snowlb_status r2 = recompute(c->adj.nck - 1)) return r2;
     int cur = 0;
     for (int k = c->adj.nck - 1; k >= 0; --k) {
-        const int len = std::min(st, n - k * st);
-        HIPCHK(c, hipMemcpyAsync(adj_slot(c, c->adj.nck), adj_slot(c, k), (size_t)c->adj.slot_bytes,
-                                 hipMemcpyDeviceToDevice, s));
+        const int len = std::min(st, n - k * st), ar = k & 1;
+        if (overlap) HIPCHK(c, hipStreamWaitEvent(s, c->adj.ev_rec[ar], 0));
         hipGraphExec_t g = nullptr;
-        if (snowlb_status r2 = adj_segment_graph(c, A, lam, len, cur, grid, &g)) return r2;
+        if (snowlb_status r2 = adj_graph(c, 1, A, lam, ar, len, cur, grid, &g)) return r2;
         HIPCHK(c, hipGraphLaunch(g, s));
         cur ^= len & 1;
+        if (overlap) HIPCHK(c, hipEventRecord(c->adj.ev_rev[ar], s));
+        if (k > 0) {
+            // interval k - 1 uses area (k - 1) % 2, last read by the reverse of interval k + 1
+            if (overlap && k + 1 < c->adj.nck) HIPCHK(c, hipStreamWaitEvent(rs, c->adj.ev_rev[(k + 1) & 1], 0));
+            if (snowlb_status r2 = recompute(k - 1)) return r2;
+        }
     }
     A.lin = lam[cur];
     e = launch_adj_finish(A, dU, c->adj.rows, c->adj.d_out, s);

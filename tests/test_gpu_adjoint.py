@@ -82,6 +82,31 @@ def test_adjoint_stride_and_repeat_invariance():
         assert np.array_equal(other[1], a[1])
 
 
+@pytest.mark.parametrize("stride", [0, 7, 33, 1])
+def test_adjoint_overlapped_schedule_is_bitwise_serial(stride, monkeypatch):
+    """The backward pass recomputes interval k - 1 on a second stream while interval k is reversed;
+    it must give exactly the serial schedule's results (strides with an odd number of intervals, a
+    one-step last interval (100 = 3 x 33 + 1), and one step per interval), also when the backward is
+    repeated after one forward (cached programs)."""
+    cfg, p, U, target = setup(48, 100)
+    monkeypatch.setenv("SNOWLB_ADJ_OVERLAP", "0")
+    a = gpu_grads(cfg, U, target, 100, stride=stride)
+    monkeypatch.setenv("SNOWLB_ADJ_OVERLAP", "1")
+    b = gpu_grads(cfg, U, target, 100, stride=stride)
+    assert b[2] == a[2] and b[3] == a[3]
+    assert np.array_equal(b[1], a[1])
+    sim = S.Sim(cfg)
+    S.snowlb_set_eps(sim.ctx, cfg["eps"])
+    sim.init(torch.from_numpy(U).float())
+    S.snowlb_adj_forward(sim.ctx, 100, stride, sim.stream)
+    seed = (2 * (sim.read("phi").double() - torch.from_numpy(target).cuda())).float().contiguous()
+    for _ in range(2):
+        dU = torch.empty_like(seed)
+        de, du0 = S.snowlb_adj_backward(sim.ctx, seed.data_ptr(), dU.data_ptr(), sim.stream)
+        assert de == a[2] and du0 == a[3]
+        assert np.array_equal(dU.double().cpu().numpy(), a[1])
+
+
 def test_autograd_function():
     n, steps = 48, 120
     cfg, p, _, target = setup(n, steps)
@@ -112,6 +137,11 @@ def test_adjoint_unsupported_configurations():
     with pytest.raises(S.SnowlbError) as e:
         S.snowlb_adj_backward(sim.ctx, g.data_ptr(), g.data_ptr(), sim.stream)
     assert e.value.status == S.ESTATE
+    for extra in (dict(stencil=6), dict(stencil=2), dict(symmetric=1)):
+        sim = S.Sim(dict(cfg, **extra)).init()
+        with pytest.raises(S.SnowlbError) as e:
+            S.snowlb_adj_forward(sim.ctx, 10, 0, sim.stream)
+        assert e.value.status == S.EUNSUPPORTED, extra
 
 
 def test_c5_full_size_gradients_against_finite_differences():
