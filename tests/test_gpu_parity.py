@@ -169,6 +169,59 @@ def test_full_size_first_steps(cfg):
             assert err <= 1e-5, (n, k, err)
 
 
+# The largest lattices the library accepts in each storage with flow: one population copy (with its
+# 16-bit references) within 0.002 % of the 4 GiB that 32-bit byte offsets can address.
+MAX_LATTICES = {"fp32": (6976, 6692), "fp16": (7104, 11196)}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_maximum_lattice_first_steps(storage):
+    """The largest accepted lattice, ventilated, after init and 3 steps, sampled where the oracle can
+    compute it: the state near a point depends only on the few cells around it, so crops of the big
+    lattice are compared with the same crops of a 512 x 96 oracle lattice with the same physics and
+    the same relative placement -- around the seed near the inlet, and at the far corners (inlet and
+    outlet columns in the last block row, where the byte offsets are largest)."""
+    nx, ny = MAX_LATTICES[storage]
+    assert S.snowlb_validate(S.make_params(dict(W.C3, nx=nx, ny=ny), storage))[0] == S.OK
+    assert S.snowlb_validate(S.make_params(dict(W.C3, nx=nx + 64, ny=ny), storage))[0] == S.EINVAL
+    ys = ny // 2
+    cfg = dict(W.C3, nx=nx, ny=ny, seed=(300.0, float(ys), 8.0))
+    ocfg = dict(W.C3, nx=512, ny=96, seed=(300.0, 48.0, 8.0))
+    o = oracle.Oracle(oracle.Params.from_dict(ocfg)).init_seed(*ocfg["seed"], ocfg["w_init"], ocfg["U0"])
+    sim = S.Sim(cfg, storage=storage).init()
+    crops = [  # (GPU rows, GPU cols, oracle rows, oracle cols)
+        (slice(ys - 40, ys + 40), slice(0, 400), slice(8, 88), slice(0, 400)),
+        (slice(ny - 30, ny), slice(nx - 60, nx), slice(10, 40), slice(452, 512)),
+        (slice(ny - 30, ny), slice(0, 60), slice(10, 40), slice(0, 60)),
+    ]
+    bar = 1e-5 if storage == "fp32" else 1e-3
+    for n in (0, 3):
+        o.step(n)
+        sim.step(n)
+        F = o.fields()
+        for k in ("phi", "U", "rho", "ux", "uy"):
+            full = sim.read(k)
+            for gr, gc, orow, ocol in crops:
+                got = full[gr, gc].double().cpu().numpy()
+                err = float(np.abs(got - F[k][orow, ocol]).max())
+                assert err <= bar, (n, k, gr, gc, err)
+            del full
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_zero_steps_is_a_no_op():
+    cfg = cfg_of(70, 37, **CASES["flow_inout"])
+    sim = S.Sim(cfg).init()
+    sim.step(5)
+    before = gpu_state(sim, 1)
+    sim.step(0)
+    assert sim.step_count == 5
+    after = gpu_state(sim, 1)
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
 def test_graph_replay_matches_plain_launches():
     cfg = cfg_of(100, 90, flow=1, inout=1, u_in=0.02, U_in=0.6)
     a = S.Sim(cfg).init()
