@@ -319,6 +319,49 @@ def test_gaussian_advection_diffusion(u):
     assert np.sqrt(np.sum((Un - Ub) ** 2) / np.sum((Ub - 0.5) ** 2)) > 10 * err
 
 
+def _stefan_slope(W0, U0=0.5, L_sat=1.6, D=0.1, nx=1024, ny=2, chunk=5000, chunks=24):
+    """Flat slab of ice (half-width 10 W0) growing into vapour at U0 with the one-sided model: the
+    slope of s^2 against t for the right front over the second half of the run."""
+    tau0 = W0 * W0 / D
+    lam = tau0 * D / (si.A2 * W0 * W0)  # beta = 0: no kinetic undercooling
+    p = oracle.Params(nx=nx, ny=ny, eps=0.0, W0=W0, tau0=tau0, lam=lam, L_sat=L_sat, tau_vap=0.5 + 3 * D)
+    o = oracle.Oracle(p)
+    x = np.arange(nx, dtype=float)
+    phi0 = np.repeat(np.tanh((10.0 * W0 - np.abs(x - nx / 2)) / (math.sqrt(2) * W0))[None, :], ny, 0)
+    U = np.where(phi0 > 0, 0.0, U0)
+    o.set_state(g=W5()[:, None, None] * U[None], h=W9()[:, None, None] * phi0[None], phip=phi0)
+    ts, ss = [], []
+    for _ in range(chunks):
+        o.step(chunk)
+        pr = o.fields()["phi"][0]
+        i = int(np.nonzero(pr[nx // 2:] < 0)[0][0]) + nx // 2
+        ts.append(o.step_count)
+        ss.append(i - 1 + pr[i - 1] / (pr[i - 1] - pr[i]) - nx / 2)
+    m = chunks // 2
+    return np.polyfit(np.array(ts[m:], float), np.array(ss[m:]) ** 2, 1)[0]
+
+
+@pytest.mark.slow
+def test_stefan_front_converges_in_W0():
+    """One-sided Stefan problem (Eq. (b) with its depletion source, flat front, beta = 0): the
+    similarity solution has s = 2 p sqrt(D t) with St = U0/L_sat = sqrt(pi) p exp(p^2) erfc(p)
+    (p = 0.22292 for U0 = 0.5, L_sat = 1.6), so d(s^2)/dt = 4 p^2 D.  The phase-field model without
+    an anti-trapping current reaches it only as W0 -> 0, with an error linear in W0: at W0 = 1 and 2
+    (lattice units) the slope is about 1.3 and 1.55 times the closed form, and the linear
+    extrapolation 2 r(1) - r(2) lands within 8 % of it.  A wrong depletion factor (L_sat instead of
+    L_sat/2), a wrong diffusivity switch or a flipped source sign miss by far more."""
+    from scipy.optimize import brentq
+    from scipy.special import erfc
+    U0, L_sat, D = 0.5, 1.6, 0.1
+    p = brentq(lambda q: math.sqrt(math.pi) * q * math.exp(q * q) * erfc(q) - U0 / L_sat, 1e-6, 5.0)
+    assert abs(p - 0.22292) < 1e-5
+    exact = 4 * p * p * D
+    r1, r2 = _stefan_slope(1.0) / exact, _stefan_slope(2.0) / exact
+    print("  Stefan slope ratios W0 = 1: %.4f, W0 = 2: %.4f, extrapolated %.4f" % (r1, r2, 2 * r1 - r2))
+    assert 1.0 < r1 < r2 < 1.6
+    assert abs(2 * r1 - r2 - 1) < 0.08
+
+
 def test_symmetric_diffusivity_inside_the_solid():
     """Thermal variant of the Sec. 3.1.1 study (diffusivity q = 1 in both phases): inside ice
     (phi = 1 everywhere, a fixed point of the phase field) a Gaussian pulse of U spreads with
@@ -351,6 +394,35 @@ def test_invalid_stencil_rejected():
         oracle.Oracle(oracle.Params(nx=8, ny=8, stencil=3))
     with pytest.raises(ValueError):
         oracle.Oracle(oracle.Params(nx=8, ny=8, symmetric=2))
+
+
+def _gaussian_error(n, sigma0, T, u=(0.02, 0.01), tau_g=0.8):
+    p = oracle.Params(nx=n, ny=n, flow=1, tau_vap=tau_g, L_sat=0.0)
+    o = oracle.Oracle(p)
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    x0 = y0 = n / 2
+    U = 0.5 + 0.1 * np.exp(-((x - x0) ** 2 + (y - y0) ** 2) / (2 * sigma0 ** 2))
+    f = np.broadcast_to(oracle.feq(1.0, *u)[:, None, None], (9, n, n)).copy()
+    o.set_state(f=f, g=oracle.geq(1.0, *u)[:, None, None] * U[None], h=_uniform_phase(n, n), phip=-np.ones((n, n)))
+    o.step(T)
+    D = (tau_g - 0.5) / 3
+    s2 = sigma0 ** 2 + 2 * D * T
+    dx = (x - x0 - u[0] * T + n / 2) % n - n / 2
+    dy = (y - y0 - u[1] * T + n / 2) % n - n / 2
+    Ua = 0.5 + 0.1 * sigma0 ** 2 / s2 * np.exp(-(dx ** 2 + dy ** 2) / (2 * s2))
+    Un = o.fields()["U"]
+    return np.sqrt(np.sum((Un - Ua) ** 2) / np.sum((Ua - 0.5) ** 2))
+
+
+def test_gaussian_advection_diffusion_second_order():
+    """Refining the pulse relative to the lattice in diffusive scaling (sigma0 10 -> 20 on a lattice
+    twice as wide, four times the steps, the lattice velocity halved: the same advected and diffused
+    shape in units of sigma0) cuts the L2 error about four-fold: the vapour solver is second-order
+    accurate."""
+    e1 = _gaussian_error(128, 10.0, 400, u=(0.02, 0.01))
+    e2 = _gaussian_error(256, 20.0, 1600, u=(0.01, 0.005))
+    print("  Gaussian L2 errors %.3e -> %.3e, ratio %.2f" % (e1, e2, e1 / e2))
+    assert 3.2 < e1 / e2 < 5.0
 
 
 def _slab(W0, U0, theta, n, eps=0.05, lam=3.0, half=8.0, L_sat=0.0):
