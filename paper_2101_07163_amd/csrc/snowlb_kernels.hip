@@ -72,6 +72,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     constexpr int NP = (FLOW ? 23 : 14) + (REF ? NR : 0);  // planes per block of a copy (d.nqb)
     constexpr uint32_t ES = sizeof(T);
     __shared__ double s_phi[LN];
+    __shared__ float s_phif[REF ? LN : 1];  // phi(t) rounded to FP32: the h references
     __shared__ float s_h[9][LN];
     __shared__ float s_ref[NR][REF ? LN : 1];
 
@@ -203,6 +204,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 for (int q = 0; q < 9; ++q) hh[q] = 0.f;
             }
             s_phi[li] = p64;
+            if (REF) s_phif[li] = (float)p64;
 #pragma unroll
             for (int q = 0; q < 9; ++q) s_h[q][li] = hh[q];
             if (REF) {
@@ -424,7 +426,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 const float fm = (REF && FLOW) ? f_ref(rR, rJx, rJy, CX[q], CY[q]) : 0.f;
                 if (xd >= 0) {
                     const uint32_t dO = ((CX[q] > 0 ? xpE : (CX[q] < 0 ? xpW : xp)) + ypd) * ES;
-                    const float href = REF ? (float)s_phi[lq] : 0.f;  // h references its holder's phi(t)
+                    const float href = REF ? s_phif[lq] : 0.f;  // h references its holder's phi(t)
                     gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][lq], IW9[q], href));
                     if (FLOW) gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
                     if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
@@ -434,7 +436,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         // outlet ghost at x = nx is a copy of this column: it streams into (nx-1, yd)
                         const uint32_t dO = (xp + ypd) * ES;
                         const int ld = own + CY[q] * LX;
-                        const float href = REF ? (float)s_phi[ld] : 0.f;
+                        const float href = REF ? s_phif[ld] : 0.f;
                         gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][ld], IW9[q], href));
                         gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
                         if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
