@@ -137,7 +137,11 @@ def test_c1_plain_128_full_run():
         report("C1 step %d phi" % t, e_phi)
         report("C1 step %d U" % t, e_U)
         assert e_phi <= 1e-4 and e_U <= 1e-4
-    assert int((phi > 0).sum()) == int(o.diag()["n_solid"])
+    # ice or vapour (phi > 0): the same decision on every cell whose oracle value lies outside the
+    # phi error bar; cells inside it may go either way in FP32
+    po = F["phi"]
+    sure = np.abs(po) > 1e-4
+    assert np.array_equal((phi > 0)[sure], (po > 0)[sure])
 
 
 def test_ventilated_small_run():

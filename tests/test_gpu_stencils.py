@@ -43,7 +43,11 @@ def test_stencil_c1_plain_128_run(stencil):
         for k, v in e.items():
             report("E%d C1 step %d %s" % (stencil, t, k), v)
             assert v <= 1e-4, (t, k)
-    assert int((phi > 0).sum()) == int(o.diag()["n_solid"])
+    # ice or vapour (phi > 0): the same decision on every cell whose oracle value lies outside the
+    # phi error bar; cells inside it may go either way in FP32
+    po = o.fields()["phi"]
+    sure = np.abs(po) > 1e-4
+    assert np.array_equal((phi > 0)[sure], (po > 0)[sure])
 
 
 @pytest.mark.parametrize("stencil", [2, 8])
