@@ -99,7 +99,8 @@ __device__ __forceinline__ void pass_a(const AdjDesc& A, const double* s_phi, co
 #pragma unroll
     for (int q = 0; q < 9; ++q) h[q] = s_h[q][c2];
     const float phi = (float)s_phi[c2];
-    const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+    // U as the forward step forms it in FP32 storage (an exact FP64 sum, rounded once)
+    const float U = (float)((((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) + (double)g[4]);
 
     // ---- forward recompute (as the step kernel)
     const double* S = s_phi + c2;

@@ -267,7 +267,16 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                     f[q] = f_dev_dec<S>(fraw[q], q, m);  // f_q - w_q
                 }
             }
-            const float U = (g[0] + g[1]) + (g[2] + g[3]) + g[4];
+            // FP32 storage closes the zeroth and first moments of each collision exactly (below): the
+            // sums of the incoming populations are then taken in FP64, where a sum of a few FP32 values
+            // is exact.  In uniform streams every cell rounds the same numbers the same way, so
+            // independent roundings of each population add up coherently into a drift of the
+            // pressure level and of the species; with the moments closed, the collision changes them
+            // by one rounding of a small population only.  16-bit storage rounds every population to
+            // 16 bits afterwards anyway and keeps the cheaper FP32 sums.
+            constexpr bool EXACT = !REF;
+            const double U64 = EXACT ? (((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) + (double)g[4] : 0.0;
+            const float U = EXACT ? (float)U64 : (g[0] + g[1]) + (g[2] + g[3]) + g[4];
 
             // ---- isotropic gradient (Sec. 3.1.1): sum over the stencil of w(|c|^2) phi(x + c) c with
             // the Table 1 weights (E4: 1/3 on axis neighbours, 1/12 on diagonals; no 1/cs^2), or the
@@ -337,10 +346,22 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             float ux = 0.f, uy = 0.f, rho = 0.f, jx = 0.f, jy = 0.f;
             float fs[9];
             if (FLOW) {
-                const float drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                double m64 = 0.0, jx64 = 0.0, jy64 = 0.0;
+                float drho;
+                if (EXACT) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) m64 += (double)f[q];
+                    jx64 = ((double)f[1] - (double)f[3]) + ((double)f[5] - (double)f[6]) + ((double)f[8] - (double)f[7]);
+                    jy64 = ((double)f[2] - (double)f[4]) + ((double)f[5] + (double)f[6]) - ((double)f[7] + (double)f[8]);
+                    drho = (float)m64;
+                    jx = (float)jx64;
+                    jy = (float)jy64;
+                } else {
+                    drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+                    jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+                    jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+                }
                 rho = 1.f + drho;
-                jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-                jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 const float pc = fminf(fmaxf(phi, -1.f), 1.f);
                 const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
                 const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
@@ -361,6 +382,20 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 Sg[0] = -sum8(Sg);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
+                if (EXACT) {
+                    // after collision the first moments are j - omega (j - rho u) + (1 - omega/2) F and the
+                    // zeroth is unchanged (Guo forcing, Sec. 2.2.1): fs_1 and fs_2 take the first moments as
+                    // remainders, then fs_0 the zeroth, with every sum in FP64
+                    const double om = d.omega_f, gu = d.guo;
+                    const double px = jx64 - om * (jx64 - (double)rho * (double)ux) + gu * (double)Fx;
+                    const double py = jy64 - om * (jy64 - (double)rho * (double)uy) + gu * (double)Fy;
+                    fs[1] = (float)(px - ((-(double)fs[3] + (double)fs[5]) + ((double)fs[8] - (double)fs[6] - (double)fs[7])));
+                    fs[2] = (float)(py - ((-(double)fs[4] + (double)fs[5]) + ((double)fs[6] - (double)fs[7] - (double)fs[8])));
+                    double s64 = 0.0;
+#pragma unroll
+                    for (int q = 1; q < 9; ++q) s64 += (double)fs[q];
+                    fs[0] = (float)(m64 - s64);
+                }
             }
 
             // ---- vapour (Sec. 2.2.2): tau_g = 1/2 + (tau_vap - 1/2) q with q = clamp((1 - phi)/2, 0, 1),
@@ -380,6 +415,8 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 sgq[0] = srcg - ((sgq[1] + sgq[2]) + (sgq[3] + sgq[4]));
 #pragma unroll
                 for (int q = 0; q < 5; ++q) gs[q] = g[q] - (g[q] - geq[q]) * itg - sgq[q];
+                if (EXACT)  // the zeroth moment after collision is U - src: gs_0 as its remainder
+                    gs[0] = (float)((U64 - (double)srcg) - (((double)gs[1] + (double)gs[2]) + ((double)gs[3] + (double)gs[4])));
             }
 
             // ---- phase field equilibrium (Eq. e) and source shares, rest population as remainder
