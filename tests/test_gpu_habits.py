@@ -88,3 +88,24 @@ def test_table2_habits_at_a_common_size():
         assert d[3] > d[6] > d[5]
         # U0 = 0.5: thinner branches as the depletion rate falls 1.8 -> 1.6 -> 1.2
         assert d[2] > d[3] > d[7]
+
+
+def test_ventilation_speeds_up_the_upstream_tips():
+    """The ventilated 1024^2 workload (Sec. 3.1.3, 3.2.2: inflow from the left): the vapour gradient is
+    steeper on the upstream side, so after 10^4 steps the tip facing the inflow (180 deg) is much longer
+    than the downstream one (0 deg) and the upstream-inclined tips (120, 240 deg) longer than the
+    downstream-inclined ones (60, 300 deg), while the crystal stays mirror-symmetric about the flow
+    axis.  Without inflow the six tips grow alike."""
+    from shapes import ray_radius
+    for u_in in (0.02, 0.0):
+        cfg = dict(W.C2, u_in=u_in)
+        sim = S.Sim(cfg).init().step(10000)
+        phi = sim.read("phi").double().cpu().numpy()
+        cx, cy = cfg["seed"][:2]
+        r = {a: ray_radius(phi, cx, cy, math.radians(a)) for a in (0, 60, 120, 180, 240, 300)}
+        print("  u_in %.2f tips %s" % (u_in, " ".join("%d:%.2f" % kv for kv in r.items())), flush=True)
+        assert abs(r[60] - r[300]) < 0.05 and abs(r[120] - r[240]) < 0.05
+        if u_in > 0:
+            assert r[180] > 1.5 * r[0] and r[120] > 1.2 * r[60]
+        else:
+            assert max(r.values()) < 1.01 * min(r.values())
