@@ -5,7 +5,7 @@
 // (collision arithmetic stays FP32):
 //   h   : m = phi(t-1) of the cell that holds the population (its phi_prev; the writer knows it from
 //         the LDS phi of the destination, the reader from its phi_prev plane);
-//   g_q : m = U of the cell the population streamed from;
+//   g_q : m = U (1 + 3 c_q . j) of the cell the population streamed from (U without flow);
 //   f_q : m = rho + 3 c_q . j of the cell the population streamed from (its first-order equilibrium,
 //         so the velocity term leaves the deviation).
 // The source cell stores its U, rho, jx, jy rounded to the 16-bit format in reference planes; writer
@@ -68,6 +68,13 @@ struct StoreBF16 {
 // that the writer and every reader produce the same bits.
 __device__ __forceinline__ float f_ref(float rho, float jx, float jy, int cx, int cy) {
     return __builtin_fmaf(3.f, (float)cx * jx + (float)cy * jy, rho);
+}
+
+// Reference of a 16-bit g_q: U (1 + 3 c_q . j) of its source (its first-order equilibrium with the
+// momentum j standing in for the velocity), with one explicit fused rounding so that the writer and
+// every reader produce the same bits.  A U reference of 0 gives 0 whatever j holds.
+__device__ __forceinline__ float g_ref(float U, float jx, float jy, int cx, int cy) {
+    return __builtin_fmaf(3.f * U, (float)cx * jx + (float)cy * jy, U);
 }
 
 // Flow populations are carried as deviations from the lattice weights, df_q = f_q - w_q, through the

@@ -70,7 +70,7 @@ __device__ __forceinline__ void decode_cell(const DomDesc& d, int par, int x, in
     for (int q = 0; q < 9; ++q) {
         float r[4];
         ref_at<S>(d, par, x - CX[q], y - CY[q], r);
-        if (q < 5) g[q] = S::dec(plane_ptr<S>(d, par, d.off_g + q)[i], W5[q], r[R_U]);
+        if (q < 5) g[q] = S::dec(plane_ptr<S>(d, par, d.off_g + q)[i], W5[q], g_ref(r[R_U], r[R_JX], r[R_JY], CX[q], CY[q]));
         f[q] = flow ? f_abs_dec<S>(plane_ptr<S>(d, par, q)[i], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]))
                     : 0.f;
     }
@@ -162,7 +162,7 @@ __global__ void k_init(DomDesc d, int par, InitArgs a) {
         float r[4] = {0.f, 0.f, 0.f, 0.f};
         if (S::kLocalRef) init_ref_at<S>(d, a, x - CX[q], y - CY[q], r);
         if (flow) plane_ptr_w<S>(d, par, q)[i] = f_dev_enc<S>(dfq[q], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
-        if (q < 5) plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], r[R_U]);
+        if (q < 5) plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], g_ref(r[R_U], r[R_JX], r[R_JY], CX[q], CY[q]));
     }
 }
 
@@ -283,7 +283,7 @@ __global__ void k_write_field(DomDesc d, int par, int field, const float* __rest
     for (int q = 0; q < 5; ++q) {
         float r[4] = {0.f, 0.f, 0.f, 0.f};
         if (S::kLocalRef && d.inout && x - CX[q] < 0) ref_at<S>(d, par, -1, y - CY[q], r);  // ghost constants
-        plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], r[R_U]);
+        plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(gq[q], IW5[q], g_ref(r[R_U], r[R_JX], r[R_JY], CX[q], CY[q]));
     }
 }
 
@@ -346,7 +346,7 @@ __global__ void k_pop_set(DomDesc d, int par, int set, const float* __restrict__
             if (set == 0)
                 plane_ptr_w<S>(d, par, q)[i] = f_abs_enc<S>(canon[q * n + c], q, f_ref(r[R_RHO], r[R_JX], r[R_JY], CX[q], CY[q]));
             else
-                plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], r[R_U]);
+                plane_ptr_w<S>(d, par, d.off_g + q)[i] = S::enc(canon[q * n + c], IW5[q], g_ref(r[R_U], r[R_JX], r[R_JY], CX[q], CY[q]));
         }
     } else if (set == 2) {
         const float ref = S::kLocalRef ? phip_ptr(d, par)[i1] : 0.f;

@@ -255,7 +255,14 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             // ---- vapour and flow populations (16-bit: references of their source cells)
             float g[5], f[9];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) g[q] = S::dec(graw[q], W5[q], REF ? s_ref[R_U][own - CY[q] * LX - CX[q]] : 0.f);
+            for (int q = 0; q < 5; ++q) {
+                float m = 0.f;
+                if (REF) {
+                    const int ls = own - CY[q] * LX - CX[q];
+                    m = FLOW ? g_ref(s_ref[R_U][ls], s_ref[R_JX][ls], s_ref[R_JY][ls], CX[q], CY[q]) : s_ref[R_U][ls];
+                }
+                g[q] = S::dec(graw[q], W5[q], m);
+            }
             if (FLOW) {
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
@@ -461,12 +468,13 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 const float Pq = hs * ia2;
                 const int lq = own + CY[q] * LX + CX[q];
                 const float fm = (REF && FLOW) ? f_ref(rR, rJx, rJy, CX[q], CY[q]) : 0.f;
+                const float gm = REF ? (FLOW ? g_ref(rU, rJx, rJy, CX[q], CY[q]) : rU) : 0.f;
                 if (xd >= 0) {
                     const uint32_t dO = ((CX[q] > 0 ? xpE : (CX[q] < 0 ? xpW : xp)) + ypd) * ES;
                     const float href = REF ? s_phif[lq] : 0.f;  // h references its holder's phi(t)
                     gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][lq], IW9[q], href));
                     if (FLOW) gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
-                    if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
+                    if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], gm));
                 }
                 if (INOUT) {
                     if (CX[q] < 0 && x == d.nx - 1) {
@@ -476,7 +484,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         const float href = REF ? s_phif[ld] : 0.f;
                         gst<T>(pout + (PH + q) * pb, dO, S::enc(Pq - B * s_h[q][ld], IW9[q], href));
                         gst<T>(pout + (PF + q) * pb, dO, f_dev_enc<S>(fs[q], q, fm));
-                        if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], rU));
+                        if (q < 5) gst<T>(pout + (PG + q) * pb, dO, S::enc(gs[q], IW5[q], gm));
                     }
                     if (CX[q] > 0 && x == 0) {
                         // inlet ghost at x = -1: equilibrium at (rho0, u_in; U_in; phi = -1); its
@@ -484,7 +492,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                         const int lg = own - CX[q] - CY[q] * LX;  // the ghost source in the LDS halo
                         float gfm = 0.f, ggm = 0.f;
                         if (REF) {
-                            ggm = s_ref[R_U][lg];
+                            ggm = g_ref(s_ref[R_U][lg], s_ref[R_JX][lg], s_ref[R_JY][lg], CX[q], CY[q]);
                             gfm = f_ref(s_ref[R_RHO][lg], s_ref[R_JX][lg], s_ref[R_JY][lg], CX[q], CY[q]);
                         }
                         gst<T>(pout + (PH + q) * pb, co * ES, S::enc(-W9[q], IW9[q], REF ? phi : 0.f));

@@ -355,6 +355,14 @@ def f_ref32(rho, jx, jy, q):
     return np.asarray(rho + 3.0 * (CXa[q] * np.asarray(jx) + CYa[q] * np.asarray(jy)), np.float32).astype(np.float64)
 
 
+def g_ref32(U, jx, jy, q):
+    """U (1 + 3 c_q . j) as the library forms it: 3U rounded to FP32, then one fused multiply-add."""
+    f = np.float32
+    s = (f(CXa[q]) * np.asarray(jx, f) + f(CYa[q]) * np.asarray(jy, f)).astype(f)
+    return np.asarray(np.asarray(f(3.0) * np.asarray(U, f), f).astype(np.float64) * s.astype(np.float64)
+                      + np.asarray(U, f).astype(np.float64), f).astype(np.float64)
+
+
 def quantize_written_state(st, storage, cfg):
     """The state as it is held after writing it in 16-bit storage: p = w (m + round(p/w - m)) with
     m = phi_prev of the cell for h, and 0 for f and g (writing them resets their reference planes);
@@ -366,7 +374,7 @@ def quantize_written_state(st, storage, cfg):
     m_g = np.zeros_like(st["g"])
     gU, gR, gJ = ghost_refs(storage, cfg) if cfg.get("inout") else (0.0, 0.0, 0.0)
     if cfg.get("inout"):
-        m_g[1, :, 0] = gU
+        m_g[1, :, 0] = g_ref32(gU, gJ, 0.0, 1)
     out["g"] = decode32(w5, m_g, round_fmt(st["g"] / W5[:, None, None] - m_g, storage))
     if "f" in st:
         m_f = np.zeros_like(st["f"])
@@ -379,7 +387,8 @@ def quantize_written_state(st, storage, cfg):
 
 def source_refs(qs, cfg):
     """Reference of every population after one step: for h the phi(t) of its holder; for g_q and f_q
-    the U and rho + 3 c_q . j of the cell it streamed from (inlet ghost: U_in, rho0, rho0 u_in)."""
+    U (1 + 3 c_q . j) and rho + 3 c_q . j of the cell it streamed from (U alone without flow; inlet
+    ghost: U_in, rho0, rho0 u_in)."""
     phi_t = qs["h"].sum(axis=0)
     U_t = qs["g"].sum(axis=0)
     src = lambda a, q: np.roll(np.roll(a, CYa[q], 0), CXa[q], 1)
@@ -389,9 +398,10 @@ def source_refs(qs, cfg):
         rho = qs["f"].sum(axis=0)
         jx = (CXa[:, None, None] * qs["f"]).sum(axis=0)
         jy = (CYa[:, None, None] * qs["f"]).sum(axis=0)
+        refs["g"] = np.stack([src(U_t, q) * (1 + 3 * (CXa[q] * src(jx, q) + CYa[q] * src(jy, q))) for q in range(5)])
         refs["f"] = np.stack([src(rho, q) + 3 * (CXa[q] * src(jx, q) + CYa[q] * src(jy, q)) for q in range(9)])
     if cfg.get("inout"):
-        refs["g"][1, :, 0] = cfg["U_in"]
+        refs["g"][1, :, 0] = cfg["U_in"] * (1 + 3 * cfg["rho0"] * cfg["u_in"])
         if "f" in qs:
             for q in (1, 5, 8):
                 refs["f"][q, :, 0] = cfg["rho0"] + 3 * CXa[q] * cfg["rho0"] * cfg["u_in"]
@@ -399,7 +409,7 @@ def source_refs(qs, cfg):
             for q in (3, 6, 7):
                 refs["f"][q, :, -1] = np.roll(rho[:, -1] + 3 * (CXa[q] * jx[:, -1] + CYa[q] * jy[:, -1]), CYa[q])
         for q in (3,):
-            refs["g"][q, :, -1] = U_t[:, -1]
+            refs["g"][q, :, -1] = U_t[:, -1] * (1 + 3 * CXa[q] * jx[:, -1]) if "f" in qs else U_t[:, -1]
     return refs
 
 
@@ -459,7 +469,7 @@ def test_half_storage_c1_plain_128(storage):
 def test_ventilated_512_long_run(storage):
     """The 2048^2 half-storage workload's physics (inlet u = 0.01, U_in = U0 = 0.6, seed R = 8) on a
     512^2 lattice with the seed at (150, 256), 10000 steps, against the FP64 oracle.  Errors per
-    field are printed; the phase field bar is 1e-2 for FP16 storage.  FP32 storage is bounded at
+    field are printed; the phase field bar is 1e-2 for FP16 and BF16 storage.  FP32 storage is bounded at
     1e-3: over 10^4 ventilated steps its error grows past 1e-4 (5e-4 measured), through the pressure
     level that the open inlet/outlet pair lets FP32 rounding move."""
     cfg = dict(W.C3)
@@ -472,12 +482,8 @@ def test_ventilated_512_long_run(storage):
         report("512^2 10k %s %s" % (storage, k), v)
     if storage == "fp32":
         assert errs["phi"] <= 1e-3
-    elif storage == "fp16":
-        assert errs["phi"] <= 1e-2
     else:
-        # BF16's 8-bit mantissa misses the 1e-2 target on this 10^4-step ventilated run (measured
-        # 6.0e-2; it meets it on the 128^2 workload); bounded here at the measured level.
-        assert errs["phi"] <= 1e-1
+        assert errs["phi"] <= 1e-2
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
