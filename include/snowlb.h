@@ -47,7 +47,7 @@ typedef int32_t snowlb_status;
 #define SNOWLB_EINVAL (-1)       /* invalid argument or parameter set (checked before any GPU call) */
 #define SNOWLB_ENOMEM (-2)       /* device or host allocation failed                                */
 #define SNOWLB_EDEVICE (-3)      /* a HIP call failed; snowlb_last_error has the HIP message        */
-#define SNOWLB_EUNSUPPORTED (-4) /* valid request this build does not support                       */
+#define SNOWLB_EUNSUPPORTED (-4) /* valid request the library does not support                      */
 #define SNOWLB_ENONFINITE (-5)   /* a diagnostic found non-finite populations                       */
 #define SNOWLB_ESTATE (-6)       /* call out of order (e.g. step before init)                       */
 
