@@ -260,7 +260,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the lattice would "
-              "shard by spatial domain decomposition; see the design notes). Run with --gpus 1.",
+              "shard by spatial domain decomposition, with one exchange of boundary populations per step). "
+              "Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -13,8 +13,7 @@
  *   3. streaming (written per destination: each destination population has exactly one source)
  *   4. phi_prev <- phi, t <- t + 1
  *
- * Readings of points where the paper is silent or ambiguous are marked [Rk] and listed, with their
- * justification, in the design notes that ship with the repository:
+ * Readings of points where the paper is silent or ambiguous are marked [Rk]:
  *   R1  gradient: grad phi = sum_c w(|c|^2) phi(x+c) c with the Table 1 weights and no 1/cs^2
  *       (the Table 1 weights already satisfy sum w c c = I; with 1/cs^2 the gradient of x would be 3).
  *       E2 is the central difference of the same section (w(1) = 1/2); E4 is the default.

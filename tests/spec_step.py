@@ -1,5 +1,5 @@
-"""A second evaluator of the coupled step, written from the paper's equations and the readings of
-the design notes in vectorised numpy (test infrastructure only).
+"""A second evaluator of the coupled step, written from the paper's equations and the same readings
+of its silent points as the C oracle, in vectorised numpy (test infrastructure only).
 
 It shares no code with the C oracle and exists to check it: brute force on tiny lattices (the two
 must agree to rounding), and, because every operation here is generic over the array dtype, complex
