@@ -109,3 +109,25 @@ def test_ventilation_speeds_up_the_upstream_tips():
             assert r[180] > 1.5 * r[0] and r[120] > 1.2 * r[60]
         else:
             assert max(r.values()) < 1.01 * min(r.values())
+
+
+def test_ventilated_crystal_sheds_two_recirculation_zones():
+    """Sec. 3.2.2: in the stream the crystal forms two recirculation zones behind it.  On the 1024^2
+    ventilated workload after 10^4 steps there is reversed flow (u_x < 0, well above rounding) in the
+    fluid downstream of the solid's last column, in two zones mirror-images of each other about the
+    flow axis."""
+    cfg = W.C2
+    sim = S.Sim(cfg).init().step(10000)
+    phi = sim.read("phi").double().cpu().numpy()
+    ux = sim.read("ux").double().cpu().numpy()
+    y0 = int(cfg["seed"][1])
+    x_last = int(np.nonzero((phi > 0).any(axis=0))[0].max())
+    wake = np.zeros_like(phi, dtype=bool)
+    wake[:, x_last + 1:] = True
+    rev = wake & (phi < -0.9) & (ux < -1e-4)
+    ys, _ = np.nonzero(rev)
+    above, below = int((ys > y0).sum()), int((ys < y0).sum())
+    print("  solid ends at x = %d; reversed-flow wake cells above / below the axis: %d / %d; min u_x %.2e"
+          % (x_last, above, below, float(ux[wake & (phi < -0.9)].min())), flush=True)
+    assert above > 0 and above == below
+    assert np.array_equal(rev[y0 + 1:y0 + 200][::-1], rev[y0 - 199:y0])
