@@ -82,11 +82,12 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     const int npar = 1 - par;
 
     // XCD-aware order (optional): consecutive workgroup ids are spread over the 8 XCDs; give each
-    // XCD a contiguous run of tiles so neighbouring tiles share halo lines in that XCD's L2.
+    // XCD a contiguous run of tiles so neighbouring tiles share halo lines in that XCD's L2.  XCD x
+    // receives G/8 workgroups, one more for x < G % 8; its runs follow each other in x order, so the
+    // mapping is a permutation of the grid for any G.
     const int G = gridDim.x;
     const int b = blockIdx.x;
-    const int per_xcd = G / 8;
-    const int slot = (xcd_remap && G % 8 == 0) ? ((b % 8) * per_xcd + b / 8) : b;
+    const int slot = xcd_remap ? (b % 8) * (G / 8) + min(b % 8, G % 8) + b / 8 : b;
 
     // halo position r of the ring: the RAD rows above and below the tile, then RAD columns left and
     // right of it
