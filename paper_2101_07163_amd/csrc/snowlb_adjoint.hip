@@ -196,7 +196,11 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     __shared__ double s_red[ANT / 64];
     const int tid = threadIdx.x, tx = tid % ATX, ty = tid / ATX;
     const int ntx = (A.nx + ATX - 1) / ATX;
-    const int x0 = (blockIdx.x % ntx) * ATX, y0 = (blockIdx.x / ntx) * ATY;
+    // tiles in XCD-contiguous order (workgroup ids are dealt round-robin to the 8 XCDs; each XCD gets
+    // a contiguous run of tiles, so the halos of neighbouring tiles meet in its L2)
+    const int G = gridDim.x, bid = blockIdx.x;
+    const int tile = (bid % 8) * (G / 8) + min(bid % 8, G % 8) + bid / 8;
+    const int x0 = (tile % ntx) * ATX, y0 = (tile / ntx) * ATY;
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < A.nx && y < A.ny;
     const uint64_t pb = (uint64_t)kBlockCells * 4;  // bytes between the planes of a block
