@@ -5,14 +5,15 @@
 //   flow   : D2Q9 BGK with the solid drag force and the velocity projection (Sec. 2.2.1),
 //   vapour : D2Q5 advection-diffusion-reaction with the depletion source (Sec. 2.2.2),
 //   phase  : the capacity-form LB of Eq. (d) with the equilibrium of Eq. (e) (Sec. 2.2.3),
-// with the E4 isotropic gradient of Table 1 (Sec. 3.1.1) and the anisotropy of Sec. 2.1.
+// with an isotropic gradient of Table 1 (Sec. 3.1.1; E4 by default, or E2, E6, E8) and the anisotropy of
+// Sec. 2.1.
 //
 // The step is bound by HBM bandwidth (about 2 flop per byte against a balance of about 20), so the
 // kernel is built around memory traffic: every population is read once and written once per step,
 // and a 64 x 4 tile's populations are one contiguous run of memory (planes side by side per block,
 // see cell_index).  The only neighbour data the step needs -- phi at the eight neighbours
 // (gradient) and h_q at x + c_q (the destination term of Eq. (d)) -- is staged in LDS from a
-// one-cell halo of the 9 h planes, so halo re-reads hit LDS/L2 instead of HBM.
+// halo of the 9 h planes (one cell wide, two for E6/E8), so halo re-reads hit LDS/L2 instead of HBM.
 //
 // Streaming is "push": Eq. (d) evaluates a_s^2 at the source node and needs the destination's own
 // pre-collision h_q(x + c_q, t), so each cell writes h'_q(x + c_q) = P_q(x) - B(x) h_q(x + c_q, t),
@@ -188,7 +189,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             }
         }
         // Decode h of one staged position and write phi, h and the 16-bit references to LDS.  phi is
-        // summed in FP64: it is close to -1 or 1 in the bulk, and an E4 gradient of FP32 sums would
+        // summed in FP64: it is close to -1 or 1 in the bulk, and a gradient of FP32 sums would
         // carry cancellation error of order 1e-7 / |grad phi| into the direction of the normal, i.e.
         // into a and N where |grad phi| is small.  h is stored against its holder's phi_prev.
         auto stage = [&](bool real, const T raw[9], float href, const T refs[NR], int li, float hh[9]) {
