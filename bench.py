@@ -16,9 +16,12 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -126,7 +129,37 @@ def stencil_family(S, torch, W, cfg, storage, steps, tile):
         study["E%d_MLUPS" % st] = round(c["nx"] * c["ny"] * 20000 / wall / 1e6, 1)
         del sim
     res["study"] = study
+    res["fourfold"] = fourfold_setup(S, torch, W, tile)
     return res
+
+
+def axis_tip(phi, cx, cy):
+    """Distance from the seed centre to the phi = 0 crossing along the +x lattice axis (linear
+    interpolation between the last ice node and the next one)."""
+    row = phi[int(cy), int(cx):]
+    i = int(np.nonzero(row >= 0)[0][-1])
+    return i + float(row[i] / (row[i] - row[i + 1]))
+
+
+def fourfold_setup(S, torch, W, tile):
+    """The four-fold validation set-up of Sec. 3.1.2 at its own sizes and lengths: tip distance at
+    the end and the dimensionless tip velocity V d0 / D over the last fifth of the run."""
+    a1 = 5.0 * math.sqrt(2.0) / 8.0
+    out = {}
+    for c in (W.FOURFOLD, W.FOURFOLD_055):
+        sim = S.Sim(c, tile=tile).init()
+        n = c["steps"]
+        t_a = (4 * n) // 5
+        sim.step(t_a)
+        r_a = axis_tip(sim.read("phi").cpu().numpy(), *c["seed"][:2])
+        sim.step(n - t_a)
+        r_b = axis_tip(sim.read("phi").cpu().numpy(), *c["seed"][:2])
+        d0 = a1 * c["W0"] / c["lam"]
+        D = (c["tau_vap"] - 0.5) / 3.0
+        out[c["name"]] = {"U0": c["U0"], "steps": n, "tip_cells": round(r_b, 2),
+                          "V_d0_over_D": round((r_b - r_a) / (n - t_a) * d0 / D, 5)}
+        del sim
+    return out
 
 
 def habit_sweep(S, torch, W, steps=20000, warmup=200):

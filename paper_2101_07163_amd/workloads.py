@@ -60,6 +60,21 @@ F1 = _cfg(name="f1_stencil_study_800", nx=800, ny=800, flow=0, inout=0, W0=1.25,
           tau_vap=0.95, lam=10.0, eps=0.05, L_sat=1.0, U0=0.3, symmetric=1, stencil=4,
           seed=(400.0, 400.0, 10.0), w_init=1.25, steps=100000)
 
+# The four-fold validation set-up of Sec. 3.1.2 in lattice units: W0 = tau0 = 1 with dx = 0.4 W0 and
+# dt = 0.008 tau0, i.e. W0 = 2.5, tau0 = 125 (W0^2/tau0 = 0.05); kappa = 4 -> D = 4 dt/dx^2 = 0.2
+# (tau_vap = 1/2 + 3 D = 1.1); lambda = tau0 kappa / (a2 W0^2) = 6.3826 in the set-up's own units, which
+# makes the kinetic coefficient vanish; eps = 0.05 with four-fold symmetry; the symmetric thermal model
+# (q = 1, L_sat = 1, undercooling U0); seed R = 10 at the centre with interface width W0.  U0 = 0.3
+# runs on 1000^2 for 1.3e5 steps, U0 = 0.55 on 500^2 (run length not stated; 1.8e4 steps, 144 tau0,
+# bring its tips to about 185 cells, inside the box).  The dimensionless tip velocity is V d0 / D
+# with d0 = a1 W0 / lambda, all in lattice units.
+FOURFOLD = _cfg(name="f1_fourfold_1000", nx=1000, ny=1000, flow=0, inout=0, n_fold=4, W0=2.5, tau0=125.0,
+                tau_vap=1.1, lam=4.0 / 0.6267, eps=0.05, L_sat=1.0, U0=0.3, symmetric=1, stencil=4,
+                seed=(500.0, 500.0, 10.0), w_init=2.5, steps=130000)
+FOURFOLD_055 = dict(FOURFOLD, name="f1_fourfold_500", nx=500, ny=500, U0=0.55, seed=(250.0, 250.0, 10.0),
+                    steps=18000)
+
+
 # Table 2 (Sec. 3.2.1): the seven plate-regime morphologies, (number, name, U0, L_sat).  The lattice
 # set-up of each row is units.plate_regime(U0, L_sat).
 TABLE2 = (

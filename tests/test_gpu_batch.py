@@ -91,3 +91,39 @@ def test_batch_mixes_stencils_of_one_reach(stencils, symmetric):
         want = fields(solo.read)
         for k in got:
             assert np.array_equal(got[k], want[k]), (i, k)
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_batched_16bit_storage_equals_solo_bitwise(storage):
+    """16-bit deviation storage in a batch: the reference planes follow each domain's populations, so
+    every member must still evolve bitwise as its solo run."""
+    cfgs = small_domains()
+    b = S.Batch(cfgs, storage=storage).init().step(53)
+    for i, cfg in enumerate(cfgs):
+        solo = S.Sim(cfg, storage=storage).init().step(53)
+        got = fields(lambda k: b.read(i, k))
+        want = fields(solo.read)
+        for k in got:
+            assert np.array_equal(got[k], want[k]), (storage, i, k)
+
+
+def test_batched_no_flow_periodic():
+    """A batch of periodic lattices without flow (the thermal-style sweep: g and h only), uneven
+    sizes including ragged tiles: bitwise equal to solo runs, one member against the FP64 oracle."""
+    base = dict(W.COMMON)
+    cfgs = []
+    for i, (nx, ny, eps, U0) in enumerate([(70, 70, 0.05, 0.5), (128, 40, 0.03, 0.7), (33, 97, 0.08, 0.4)]):
+        d = dict(base)
+        d.update(name="p%d" % i, nx=nx, ny=ny, flow=0, inout=0, eps=eps, U0=U0, seed=(nx // 2, ny // 2, 5.0),
+                 w_init=1.0)
+        cfgs.append(d)
+    b = S.Batch(cfgs).init().step(80)
+    for i, cfg in enumerate(cfgs):
+        solo = S.Sim(cfg).init().step(80)
+        for k in ("phi", "U"):
+            assert np.array_equal(b.read(i, k).cpu().numpy(), solo.read(k).cpu().numpy()), (i, k)
+    cfg = cfgs[2]
+    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], 1.0, cfg["U0"]).step(80)
+    F = o.fields()
+    for k in ("phi", "U"):
+        assert np.abs(b.read(2, k).double().cpu().numpy() - F[k]).max() < 1e-5, k

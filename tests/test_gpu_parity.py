@@ -90,6 +90,25 @@ def test_one_step_symmetric_diffusivity(case):
         assert err < 2e-6, k
 
 
+@pytest.mark.parametrize("n_fold,kappa_N", [(4, 1.0), (4, 2.0), (6, 2.0)])
+@pytest.mark.parametrize("case", list(CASES))
+def test_one_step_anisotropy_variants(case, n_fold, kappa_N):
+    """Four-fold anisotropy (Sec. 3.1.2) and the flux factor 2 of the literal reading of the
+    anisotropic term: both are runtime switches of the same kernel."""
+    nx, ny = 70, 37
+    cfg = cfg_of(nx, ny, n_fold=n_fold, kappa_N=kappa_N, eps=0.07, **CASES[case])
+    st = W.random_state(nx, ny, seed=17 * n_fold + int(kappa_N), flow=bool(cfg["flow"]))
+    o, sim = load_both(cfg, st)
+    o.step(1)
+    sim.step(1)
+    want = o.get_state()
+    got = gpu_state(sim, cfg["flow"])
+    for k in got:
+        err = np.abs(got[k] - want[k]).max()
+        report("%d-fold kN %g %s %s" % (n_fold, kappa_N, case, k), err)
+        assert err < 2e-6, k
+
+
 @pytest.mark.parametrize("stencil", [4, 8])
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("case", list(CASES))
