@@ -110,6 +110,29 @@ def test_one_step_anisotropy_variants(case, n_fold, kappa_N):
 
 
 @pytest.mark.parametrize("stencil", [4, 8])
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("shape", [(2, 2), (3, 2), (2, 5), (5, 3), (65, 5)])
+def test_degenerate_lattices(case, shape, stencil):
+    """The smallest lattices the library accepts, and one a cell past a 64 x 4 tile in each direction:
+    the periodic stencil wraps onto the cell itself and onto its own images (E8 reaches two cells),
+    inlet and outlet columns are neighbours or the same column's ghosts, and most lanes of the
+    workgroup are idle.  One step from an arbitrary state, then 25 more, against the oracle."""
+    nx, ny = shape
+    cfg = cfg_of(nx, ny, stencil=stencil, **CASES[case])
+    st = W.random_state(nx, ny, seed=nx * 31 + ny, flow=bool(cfg["flow"]))
+    o, sim = load_both(cfg, st)
+    for n, bar in ((1, 2e-6), (25, 2e-5)):
+        o.step(n)
+        sim.step(n)
+        want = o.get_state()
+        got = gpu_state(sim, cfg["flow"])
+        for k in got:
+            err = np.abs(got[k] - want[k]).max()
+            report("E%d %s %s +%d %s" % (stencil, case, shape, n, k), err)
+            assert err < bar, (n, k)
+
+
+@pytest.mark.parametrize("stencil", [4, 8])
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("case", list(CASES))
 def test_tile_configurations_bitwise_identical(case, storage, stencil):
