@@ -3,7 +3,7 @@
 // For a loss L(phi_T), the adjoint lambda_t = dL/d(state at t) obeys lambda_t = (dF/ds)^T lambda_{t+1}
 // where F is one step of the phase field (Eq. (d)/(e), anisotropy of Sec. 2.1, E4 gradient of
 // Table 1) and the vapour ADR solver (Sec. 2.2.2) with u = 0.  Each reverse step is one kernel,
-// k_adj, over 64 x 8 tiles, in two passes:
+// k_adj, over 64 x 16 tiles, in two passes:
 //   pass A (per position p of the tile and of its one-cell ring): recompute the forward quantities of
 //     p from the stored state at t (phi with its halo for the gradient, a, N, eta, Q, h_eq, h*), take
 //     lambda_{t+1} of the populations p emitted (at p + c_q), and form every adjoint that is local to
@@ -32,7 +32,7 @@ __device__ constexpr float AW9[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9
                                      1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 __device__ constexpr float AW5[5] = {1.f / 3.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f, 1.f / 6.f};
 
-constexpr int ATX = 64, ATY = 8, ANT = ATX * ATY;
+constexpr int ATX = 64, ATY = 16, ANT = ATX * ATY;
 constexpr int ALX = ATX + 2, ALY = ATY + 2, ALN = ALX * ALY;
 
 // i mod n for any i (one add or subtract in the common case: neighbours and halos of wide lattices)
@@ -57,7 +57,8 @@ __device__ __forceinline__ int ring_slot(int r) {
     if (r < 2 * ALX + ATY) return (1 + r - 2 * ALX) * ALX;
     return (1 + r - 2 * ALX - ATY) * ALX + ALX - 1;
 }
-// One reverse step is one kernel over 64 x 8 tiles.  Pass B at a cell gathers B(x - c_q) and
+// One reverse step is one kernel over 64 x 16 tiles (1024 lanes, one workgroup per CU at 512^2;
+// the one-cell ring is 16 % of the tile).  Pass B at a cell gathers B(x - c_q) and
 // Gbar(x - c_k) from pass A at its eight neighbours, so each workgroup runs pass A on its tile and
 // on the one-cell ring around it (the ring positions recomputed by both neighbouring workgroups
 // from the same inputs with the same code, hence bitwise equal), which needs h and phi on a two-cell

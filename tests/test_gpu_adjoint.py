@@ -54,9 +54,9 @@ def test_adjoint_matches_oracle_adjoint(n, steps):
     assert abs(du0 - dU.sum()) <= 1e-9 * abs(du0) + 1e-9
 
 
-@pytest.mark.parametrize("nx,ny,steps,R", [(70, 37, 80, 6.0), (65, 9, 60, 3.0), (5, 3, 20, 1.5), (2, 2, 20, 0.7)])
+@pytest.mark.parametrize("nx,ny,steps,R", [(70, 37, 80, 6.0), (65, 17, 60, 3.0), (5, 3, 20, 1.5), (2, 2, 20, 0.7)])
 def test_adjoint_on_ragged_and_degenerate_lattices(nx, ny, steps, R):
-    """Rectangular lattices that are ragged against the 64 x 8 reverse tiles (70 x 37; 65 x 9, a cell
+    """Rectangular lattices that are ragged against the 64 x 16 reverse tiles (70 x 37; 65 x 17, a cell
     past a tile each way) and the smallest ones, where the periodic ring of a tile wraps onto the tile
     itself: every gradient against the oracle's discrete adjoint.  On 5 x 3 the crystal fills the
     lattice and its nearly uniform phase field makes the gradient direction ill-conditioned after about
