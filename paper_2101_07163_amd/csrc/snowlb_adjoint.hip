@@ -43,6 +43,13 @@ __device__ __forceinline__ int wrapn(int i, int n) {
     return i;
 }
 
+// The y part of cell_index with a full-rate 24-bit multiply: the host accepts lattices of at most
+// 65536 x 65536 cells, i.e. fewer than 2^14 block rows and a block-row stride (64 nbx nq, nq <= 14)
+// below 2^24 elements.
+__device__ __forceinline__ uint32_t ypart24(int nbx, int nq, int y) {
+    return __umul24((uint32_t)(y >> 2), ((uint32_t)nbx * (uint32_t)nq) << 8) + ((uint32_t)(y & 3) << 6);
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -78,12 +85,14 @@ struct Nb {
 };
 __device__ __forceinline__ Nb nb_of(const AdjDesc& A, int gx, int gy) {
     Nb n;
-    n.xp = cell_xpart(wrapn(gx, A.nx), kAdjPlanes);
-    n.xE = cell_xpart(wrapn(gx + 1, A.nx), kAdjPlanes);
-    n.xW = cell_xpart(wrapn(gx - 1, A.nx), kAdjPlanes);
-    n.yp = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy, A.ny));
-    n.yN = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy + 1, A.ny));
-    n.yS = cell_ypart(A.nbx, kAdjPlanes, wrapn(gy - 1, A.ny));
+    // the position wrapped once; its neighbours then step over at most one edge
+    const int wx = wrapn(gx, A.nx), wy = wrapn(gy, A.ny);
+    n.xp = cell_xpart(wx, kAdjPlanes);
+    n.xE = cell_xpart(wx + 1 == A.nx ? 0 : wx + 1, kAdjPlanes);
+    n.xW = cell_xpart(wx == 0 ? A.nx - 1 : wx - 1, kAdjPlanes);
+    n.yp = ypart24(A.nbx, kAdjPlanes, wy);
+    n.yN = ypart24(A.nbx, kAdjPlanes, wy + 1 == A.ny ? 0 : wy + 1);
+    n.yS = ypart24(A.nbx, kAdjPlanes, wy == 0 ? A.ny - 1 : wy - 1);
     return n;
 }
 
@@ -220,7 +229,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     if (active) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, on.dest(q));
-        lpp = gld<float>((const GMEM char*)A.lppin, (cell_xpart(x, 1) + cell_ypart(A.nbx, 1, y)) * 4u);
+        lpp = gld<float>((const GMEM char*)A.lppin, (cell_xpart(x, 1) + ypart24(A.nbx, 1, y)) * 4u);
 #pragma unroll
         for (int q = 0; q < 9; ++q) lo[q] = gld<float>(lin + (5 + q) * pb, on.at());
     }
@@ -239,7 +248,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     for (int r = tid; r < L2N; r += ANT) {
         const int lx = r % L2X, ly = r / L2X;
         const uint32_t o =
-            (cell_xpart(wrapn(x0 + lx - 2, A.nx), kAdjPlanes) + cell_ypart(A.nbx, kAdjPlanes, wrapn(y0 + ly - 2, A.ny))) * 4u;
+            (cell_xpart(wrapn(x0 + lx - 2, A.nx), kAdjPlanes) + ypart24(A.nbx, kAdjPlanes, wrapn(y0 + ly - 2, A.ny))) * 4u;
         double p = 0.0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -265,7 +274,7 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
             const uint32_t io = on.at();
 #pragma unroll
             for (int q = 0; q < 5; ++q) gst<float>(lout + q * pb, io, lgo[q]);
-            gst<float>((GMEM char*)A.lppout, (cell_xpart(x, 1) + cell_ypart(A.nbx, 1, y)) * 4u, lppo);
+            gst<float>((GMEM char*)A.lppout, (cell_xpart(x, 1) + ypart24(A.nbx, 1, y)) * 4u, lppo);
         } else {
             deps = 0.0;
         }
