@@ -528,6 +528,35 @@ def test_ventilated_512_long_run(storage):
         assert errs["phi"] <= 1e-2
 
 
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_crop_10000.npz")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_c3_2048_crop_against_oracle(storage):
+    """The half-storage workload at its own size against the FP64 oracle: the 2048^2 ventilated
+    lattice over its 10^4 steps in each storage format, compared on the 512^2 crop around the crystal
+    (rows 768..1279, columns 44..555) with the oracle's fields after the same run, stored (rounded to
+    float32) by tests/golden/make_c3_crop.py.  Measured phase-field errors: FP32 2.4e-4, FP16 7.4e-3,
+    BF16 1.5e-2.  FP32 is held to 1e-3 as in the 512^2 run (over 10^4 ventilated steps its error
+    passes 1e-4), FP16 to the 1e-2 half-storage target.  BF16 misses that target at this size (its
+    8-bit mantissa, on deviations that are largest on the moving interface, where the maximum sits);
+    it is held to 2e-2 so that a regression still fails."""
+    data = np.load(GOLDEN_C3)
+    cfg = W.C3
+    (r0, r1), (c0, c1) = cfg["crop"]
+    assert int(data["steps"]) == cfg["steps"]
+    assert list(data["rows"]) == [r0, r1] and list(data["cols"]) == [c0, c1]
+    sim = S.Sim(cfg, storage=storage).init().step(cfg["steps"])
+    errs = {}
+    for k in ("phi", "U", "rho", "ux", "uy"):
+        got = sim.read(k)[r0:r1, c0:c1].double().cpu().numpy()
+        errs[k] = float(np.abs(got - data[k].astype(np.float64)).max())
+        report("2048^2 crop 10k %s %s" % (storage, k), errs[k])
+    del sim
+    torch.cuda.empty_cache()
+    assert errs["phi"] <= {"fp32": 1e-3, "fp16": 1e-2, "bf16": 2e-2}[storage]
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_write_field_sets_a_consistent_state(storage):
     """snowlb_write_field on a ventilated lattice: phi and U read back within the storage rounding,
