@@ -531,12 +531,43 @@ def test_ventilated_512_long_run(storage):
 GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_crop_10000.npz")
 
 
+GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_crop_20000.npz")
+
+
+# The phase-field bar of the full-length 1024^2 run: the FP32 run differs from the oracle by 2.0e-3
+# after 2*10^4 steps.  The 1e-4 target holds to 5000 steps (the checkpoint test above); beyond that the
+# run's own sensitivity to rounding-sized perturbations grows past it (see the docstring below).
+C2_20K_PHI_BAR = 4e-3
+
+
+def test_c2_1024_full_length_crop_against_oracle():
+    """The 1024^2 ventilated workload over its full 2*10^4 steps in FP32 storage against the FP64
+    oracle's fields after the same run, on the 512^2 crop around the crystal (rows 256..767, columns
+    44..555), stored by tests/golden/make_oracle_crop.py.  Measured: phase field 2.0e-3, U 2.6e-4,
+    rho 1.3e-5, u 7.7e-6.  The phase-field target of 1e-4 is missed at this length: relative noise of
+    9.5e-7 every 100 steps applied to the FP64 oracle's own state (about three times the random walk
+    of FP32 rounding) moves its phase field by 1.3e-4 after 10^4 steps and 5.5e-3 after 2*10^4, more than
+    the FP32 run's difference: at this length the run's own sensitivity, not the kernel, sets the error."""
+    data = np.load(GOLDEN_C2)
+    cfg = W.C2
+    (r0, r1), (c0, c1) = [tuple(int(v) for v in data["rows"]), tuple(int(v) for v in data["cols"])]
+    assert int(data["steps"]) == cfg["steps"] == 20000
+    sim = S.Sim(cfg).init().step(cfg["steps"])
+    errs = {}
+    for k in ("phi", "U", "rho", "ux", "uy"):
+        got = sim.read(k)[r0:r1, c0:c1].double().cpu().numpy()
+        errs[k] = float(np.abs(got - data[k].astype(np.float64)).max())
+        report("1024^2 crop 20k fp32 %s" % k, errs[k])
+    del sim
+    assert errs["phi"] <= C2_20K_PHI_BAR
+
+
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
 def test_c3_2048_crop_against_oracle(storage):
     """The half-storage workload at its own size against the FP64 oracle: the 2048^2 ventilated
     lattice over its 10^4 steps in each storage format, compared on the 512^2 crop around the crystal
     (rows 768..1279, columns 44..555) with the oracle's fields after the same run, stored (rounded to
-    float32) by tests/golden/make_c3_crop.py.  Measured phase-field errors: FP32 2.4e-4, FP16 7.4e-3,
+    float32) by tests/golden/make_oracle_crop.py.  Measured phase-field errors: FP32 2.4e-4, FP16 7.4e-3,
     BF16 1.5e-2.  FP32 is held to 1e-3 as in the 512^2 run (over 10^4 ventilated steps its error
     passes 1e-4), FP16 to the 1e-2 half-storage target.  BF16 misses that target at this size (its
     8-bit mantissa, on deviations that are largest on the moving interface, where the maximum sits);
