@@ -81,6 +81,28 @@ def test_adjoint_on_ragged_and_degenerate_lattices(nx, ny, steps, R):
     assert np.linalg.norm(dU - dUo) / np.linalg.norm(dUo) < 1e-3
 
 
+@pytest.mark.parametrize("n_fold,kappa_N", [(4, 1.0), (4, 2.0), (6, 2.0)])
+def test_adjoint_anisotropy_variants(n_fold, kappa_N):
+    """Four-fold anisotropy and the flux factor 2 (runtime switches of the forward step, and of the
+    reverse step's derivative of a and N): every gradient against the oracle's discrete adjoint."""
+    n, steps = 48, 200
+    cfg = dict(W.COMMON)
+    cfg.update(nx=n, ny=n, flow=0, inout=0, eps=0.04, n_fold=n_fold, kappa_N=kappa_N, seed=(n / 2, n / 2, 5.0),
+               w_init=1.0, U0=0.5)
+    rng = np.random.default_rng(7 * n_fold + int(kappa_N))
+    U = (0.5 + 0.02 * rng.standard_normal((n, n))).astype(np.float32).astype(np.float64)
+    p = oracle.Params.from_dict(cfg)
+    target = oracle.final_phi(dataclasses.replace(p, eps=0.06), cfg["seed"], 1.0, 0.55 + 0 * U, steps)
+    L, dU, de, du0 = gpu_grads(cfg, U, target, steps)
+    Lo, dUo, deo, _ = oracle.adjoint(p, cfg["seed"], 1.0, U, target, steps)
+    print("  %d-fold kN %g  L %.6e / %.6e  deps %.6e / %.6e  dU0 %.6e / %.6e" % (n_fold, kappa_N, L, Lo, de, deo, du0,
+                                                                                dUo.sum()))
+    assert rel(L, Lo) < 1e-4
+    assert rel(de, deo) < 1e-3
+    assert rel(du0, dUo.sum()) < 1e-3
+    assert np.linalg.norm(dU - dUo) / np.linalg.norm(dUo) < 1e-3
+
+
 def test_adjoint_matches_finite_differences():
     n, steps = 64, 400
     cfg, p, U, target = setup(n, steps)
