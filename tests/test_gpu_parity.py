@@ -268,10 +268,11 @@ def test_zero_steps_is_a_no_op():
         assert np.array_equal(before[k], after[k]), k
 
 
-def test_graph_replay_matches_plain_launches():
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_graph_replay_matches_plain_launches(storage):
     cfg = cfg_of(100, 90, flow=1, inout=1, u_in=0.02, U_in=0.6)
-    a = S.Sim(cfg).init()
-    b = S.Sim(cfg).init()
+    a = S.Sim(cfg, storage=storage).init()
+    b = S.Sim(cfg, storage=storage).init()
     os.environ["SNOWLB_NO_GRAPH"] = "1"
     try:
         a.step(69)
@@ -283,12 +284,15 @@ def test_graph_replay_matches_plain_launches():
         assert np.array_equal(sa[k], sb[k]), k
 
 
-def test_save_load_resume_bitwise():
-    cfg = cfg_of(90, 70, flow=1, inout=0)
-    a = S.Sim(cfg).init().step(25)
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_save_load_resume_bitwise(storage):
+    """A saved state (16-bit storage: the deviations with their reference planes and phi_prev)
+    resumes bitwise where the uninterrupted run continues."""
+    cfg = cfg_of(90, 70, flow=1, inout=1, u_in=0.02, U_in=0.6)
+    a = S.Sim(cfg, storage=storage).init().step(25)
     buf = a.save_state()
     a.step(30)
-    b = S.Sim(cfg).load_state(buf)
+    b = S.Sim(cfg, storage=storage).load_state(buf)
     assert b.step_count == 25
     b.step(30)
     sa, sb = gpu_state(a, 1), gpu_state(b, 1)
