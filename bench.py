@@ -257,18 +257,27 @@ def adjoint_ratio(S, torch, W):
             "plain_forward_MLUPS": round(cells * n / (plain_ms * 1e-3) / 1e6, 1)}
 
 
-def cpu_baseline(cfg, seconds):
+def cpu_baseline(cfg, seconds, threads=0):
+    """The FP64 oracle timed on a bounded sample of the workload (whole steps of the full lattice from
+    the seeded initial state), on all host threads or on `threads` of them."""
     import oracle
-    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
-    o.step(1)  # first-touch of the buffers outside the timed sample
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        o.step(1)
-        n += 1
-    dt = time.perf_counter() - t0
+    all_threads = oracle.threads()
+    if threads:
+        oracle.set_threads(threads)
+    try:
+        o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
+        o.step(1)  # first-touch of the buffers outside the timed sample
+        n = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            o.step(1)
+            n += 1
+        dt = time.perf_counter() - t0
+        used = oracle.threads()
+    finally:
+        oracle.set_threads(all_threads)
     cells = cfg["nx"] * cfg["ny"]
-    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.threads(),
+    return {"value": round(cells * n / dt / 1e6, 3), "unit": "MLUPS", "cores": used,
             "kind": "oracle",
             "sample": "%s, FP64 oracle, %d steps of the full %dx%d lattice from the seeded initial "
                       "state (%.1f s)" % (cfg["name"], n, cfg["nx"], cfg["ny"], dt)}
@@ -382,6 +391,9 @@ def main():
         log("CPU baseline: FP64 oracle for %.0f s" % args.cpu_seconds)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
         log("CPU baseline %s" % out["cpu_baseline"])
+        if "extras" in out:  # the same oracle on one thread, for a per-core figure
+            out["extras"]["cpu_baseline_1thread"] = cpu_baseline(cfg, min(5.0, args.cpu_seconds), threads=1)
+            log("CPU baseline, one thread %s" % out["extras"]["cpu_baseline_1thread"])
     print(json.dumps(out), flush=True)
 
 

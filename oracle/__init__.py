@@ -76,6 +76,7 @@ def lib():
         L.orc_aniso.argtypes = [P(OrcParams), d, d, dp, dp, dp]
         L.orc_grad.argtypes = [P(OrcParams), dp, dp, dp]
         L.orc_threads.restype = ctypes.c_int32
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
         L.orc_adj_run.restype = d
         L.orc_adj_run.argtypes = [P(OrcParams), d, d, d, d, dp, dp, ctypes.c_int32, ctypes.c_int32, dp, dp,
                                   ctypes.c_void_p]
@@ -198,6 +199,11 @@ class Oracle:
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads of the following oracle calls."""
+    lib().orc_set_threads(int(n))
 
 
 def feq(rho, ux, uy):

@@ -85,6 +85,15 @@ int32_t orc_threads(void)
 #endif
 }
 
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ---------------------------------------------------------------- building blocks */
 
 /* Second-order Hermite equilibrium of the isothermal D2Q9 lattice (Sec. 2.2.1, f_eq). */

@@ -88,6 +88,8 @@ double orc_loss(const orc_params* p, double xs, double ys, double R, double w_in
 
 /* Threads the oracle runs on (OpenMP). */
 int32_t orc_threads(void);
+/* Number of OpenMP threads of the following calls (n > 0). */
+void orc_set_threads(int32_t n);
 
 #ifdef __cplusplus
 }
