@@ -218,10 +218,13 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     const GMEM char* lin = (const GMEM char*)A.lin;
     GMEM char* lout = (GMEM char*)A.lout;
 
-    // ---- global loads, all issued before the barrier.  This lane's own position (wrapped into the
+    // ---- global loads before the barrier: what pass A on the tile needs.  Values used only later
+    // (the ring's inputs, lambda_h(t + 1) of the cell itself for pass B) are loaded where they are
+    // used, which keeps them out of the registers live across the staging: 105 VGPRs instead of
+    // 123, and a backward pass about 9 % shorter.  This lane's own position (wrapped into the
     // lattice for lanes outside it: their slots are halo of active neighbours) ...
     const Nb on = nb_of(A, x, y);
-    float g[5], lh[9], lg[5] = {}, lo[9] = {}, lpp = 0.f;
+    float g[5], lh[9], lg[5] = {}, lpp = 0.f;
 #pragma unroll
     for (int q = 0; q < 5; ++q) g[q] = gld<float>(st + q * pb, on.at());
 #pragma unroll
@@ -230,20 +233,12 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
 #pragma unroll
         for (int q = 0; q < 5; ++q) lg[q] = gld<float>(lin + q * pb, on.dest(q));
         lpp = gld<float>((const GMEM char*)A.lppin, (cell_xpart(x, 1) + ypart24(A.nbx, 1, y)) * 4u);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) lo[q] = gld<float>(lin + (5 + q) * pb, on.at());
     }
-    // ... one position of the one-cell ring (pass A there needs g and lambda_h(t + 1) only) ...
+    // ... the position of the one-cell ring this lane recomputes (pass A there needs g and
+    // lambda_h(t + 1) only, loaded after the barrier) ...
     const bool has_ring = tid < RING1;
     const int r1 = has_ring ? ring_slot(tid) : 0;  // slot in the (ALX x ALY) pass-A region
     const Nb rn = nb_of(A, x0 + r1 % ALX - 1, y0 + r1 / ALX - 1);
-    float rg[5], rlh[9];
-    if (has_ring) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) rg[q] = gld<float>(st + q * pb, rn.at());
-#pragma unroll
-        for (int q = 0; q < 9; ++q) rlh[q] = gld<float>(lin + (5 + q) * pb, rn.dest(q));
-    }
     // ... and h(t) with phi(t) = sum h (FP64, as in the forward step) on the tile and two rings
     for (int r = tid; r < L2N; r += ANT) {
         const int lx = r % L2X, ly = r / L2X;
@@ -280,6 +275,11 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
         }
     }
     if (has_ring) {
+        float rg[5], rlh[9];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) rg[q] = gld<float>(st + q * pb, rn.at());
+#pragma unroll
+        for (int q = 0; q < 9; ++q) rlh[q] = gld<float>(lin + (5 + q) * pb, rn.dest(q));
         const int c2 = (r1 / ALX + 1) * L2X + r1 % ALX + 1;
         float Bv, Gx, Gy, ah_, ph_, lgo[5], lppo;
         double de_ = 0.0;
@@ -293,6 +293,9 @@ __global__ void __launch_bounds__(ANT) k_adj(AdjDesc A) {
     // ---- pass B: lambda_h,q(x, t) = lambda_h,q(x + c_q) A_h(x) - B(x - c_q) lambda_h,q(x)
     //                                + phibar(x) + sum_k W_k c_k . Gbar(x - c_k)
     if (active) {
+        float lo[9];  // lambda_h(t + 1) at the cell itself
+#pragma unroll
+        for (int q = 0; q < 9; ++q) lo[q] = gld<float>(lin + (5 + q) * pb, on.at());
         const int own = (ty + 1) * ALX + tx + 1;
 #pragma unroll
         for (int k = 1; k < 9; ++k) {  // phi(x) entered G(x - c_k) with weight W_k c_k
