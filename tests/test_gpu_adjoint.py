@@ -186,11 +186,12 @@ def test_adjoint_unsupported_configurations():
     with pytest.raises(S.SnowlbError) as e:
         S.snowlb_adj_backward(sim.ctx, g.data_ptr(), g.data_ptr(), sim.stream)
     assert e.value.status == S.ESTATE
-    for extra in (dict(stencil=6), dict(stencil=2), dict(symmetric=1)):
-        sim = S.Sim(dict(cfg, **extra)).init()
+    for extra in (dict(stencil=6), dict(stencil=2), dict(symmetric=1), dict(storage="fp16"), dict(storage="bf16")):
+        storage = extra.pop("storage", "fp32")
+        sim = S.Sim(dict(cfg, **extra), storage=storage).init()
         with pytest.raises(S.SnowlbError) as e:
             S.snowlb_adj_forward(sim.ctx, 10, 0, sim.stream)
-        assert e.value.status == S.EUNSUPPORTED, extra
+        assert e.value.status == S.EUNSUPPORTED, (extra, storage)
 
 
 def test_c5_full_size_gradients_against_finite_differences():
