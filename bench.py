@@ -4,8 +4,9 @@
 Headline: coupled MLUPS (cells x steps / s / 1e6) of the ventilated 2048 x 2048 workload (D2Q9 flow
 with the crystal as a solid, D2Q5 vapour, phase field with 6-fold anisotropy; inlet u = 0.01, seed
 R = 8 at (300, 1024)) in FP32 storage, with all state resident in HBM.  One timed "step" is one
-coupled time step (the fused kernel, replayed from a captured HIP graph); the timed region ends with
-the FP64 conservation diagnostics.  Also reported: the HBM roofline of the step kernel (algorithmic
+coupled time step (the fused kernel, replayed from captured HIP graphs); exactly --steps steps are
+timed, five times over, and the median is reported; the FP64 conservation diagnostics follow the timed
+runs and are timed on their own.  Also reported: the HBM roofline of the step kernel (algorithmic
 bytes per launch over its measured average duration), the practical copy-kernel ceiling, 16-bit
 storage variants, and the FP64 CPU oracle timed on the host cores on a bounded sample.
 
@@ -34,13 +35,18 @@ def log(*a):
 
 
 def bytes_per_update(flow: bool, storage: str) -> int:
-    """Algorithmic HBM bytes per cell update: every population read once and written once, plus
-    phi_prev (FP32) read and written; 16-bit storage also reads and writes the cell's 16-bit
-    reference values (U, and rho, jx, jy with flow)."""
+    """Algorithmic HBM bytes per cell update of the method: every population read once and written
+    once (4 B in FP32 storage, 2 B in 16-bit storage), plus phi_prev (FP32) read and written."""
     npop = 23 if flow else 14
     e = 4 if storage == "fp32" else 2
+    return npop * e * 2 + 4 * 2
+
+
+def impl_bytes_per_update(flow: bool, storage: str) -> int:
+    """Bytes per cell update this implementation moves: the algorithmic bytes, plus in 16-bit storage
+    the cell's 16-bit reference values (U, and rho, jx, jy with flow) read and written."""
     refs = 0 if storage == "fp32" else (4 if flow else 1) * 2 * 2
-    return npop * e * 2 + 4 * 2 + refs
+    return bytes_per_update(flow, storage) + refs
 
 
 def kernel_source_sha() -> str:
@@ -74,23 +80,38 @@ def load_traffic(workload: str, storage: str):
         return None
 
 
-def time_steps(S, torch, cfg, storage, steps, warmup, tile):
+REPEATS = 5  # timed repeats of the K steps; the median is reported
+
+
+def time_steps(S, torch, cfg, storage, steps, warmup, tile, repeats=REPEATS):
+    """W untimed warm-up steps, then `repeats` timed runs of exactly `steps` steps, each bracketed by
+    device synchronisation, replayed from captured graphs on the current stream; the kernel time per
+    step comes from events on that stream.  Returns the median wall time, the median event time per
+    step, the timings of every repeat, and the FP64 diagnostics taken after the timed runs (their
+    synchronisation is timed on its own)."""
     sim = S.Sim(cfg, storage=storage, tile=tile)
     sim.init()
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()  # the kernels are launched on this stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    walls, kms = [], []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kms.append(e0.elapsed_time(e1) / steps)
     t0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(steps)
-    e1.record(stream)
     diag = sim.diag()  # FP64 conservation sums; synchronises the stream
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = e0.elapsed_time(e1) / steps
-    return sim, wall, kernel_ms, diag
+    diag_ms = (time.perf_counter() - t0) * 1e3
+    return sim, float(np.median(walls)), float(np.median(kms)), diag, {
+        "wall_s": [round(w, 6) for w in walls], "kernel_ms": [round(k, 5) for k in kms],
+        "diag_ms": round(diag_ms, 3)}
 
 
 def bw_probe(S, torch, nbytes=2 << 30, reps=10):
@@ -118,14 +139,14 @@ def stencil_family(S, torch, W, cfg, storage, steps, tile):
     bpu = bytes_per_update(bool(cfg.get("flow", 0)), storage)
     res = {"workload": cfg["name"], "storage": storage}
     for st in (2, 4, 6, 8):
-        sim, wall, k_ms, _ = time_steps(S, torch, dict(cfg, stencil=st), storage, steps, 50, tile)
+        sim, wall, k_ms, _, _ = time_steps(S, torch, dict(cfg, stencil=st), storage, steps, 50, tile)
         res["E%d" % st] = {"MLUPS": round(cells * steps / wall / 1e6, 1), "kernel_avg_ms": round(k_ms, 5),
                            "GBps_algorithmic": round(cells * bpu / (k_ms * 1e-3) / 1e9, 1)}
         del sim
     study = {"workload": W.F1["name"], "steps": 20000}
     for st in (2, 4, 6, 8):
         c = dict(W.F1, stencil=st)
-        sim, wall, k_ms, _ = time_steps(S, torch, c, "fp32", 20000, 200, tile)
+        sim, wall, k_ms, _, _ = time_steps(S, torch, c, "fp32", 20000, 200, tile, repeats=1)
         study["E%d_MLUPS" % st] = round(c["nx"] * c["ny"] * 20000 / wall / 1e6, 1)
         del sim
     res["study"] = study
@@ -320,12 +341,12 @@ def main():
 
     log("workload %s %dx%d storage %s: warmup %d, timed %d steps" % (
         cfg["name"], cfg["nx"], cfg["ny"], args.storage, args.warmup, args.steps))
-    sim, wall, kernel_ms, diag = time_steps(S, torch, cfg, args.storage, args.steps, args.warmup, args.tile)
+    sim, wall, kernel_ms, diag, reps = time_steps(S, torch, cfg, args.storage, args.steps, args.warmup, args.tile)
     mlups = cells * args.steps / wall / 1e6
     bpu = bytes_per_update(flow, args.storage)
     achieved = cells * bpu / (kernel_ms * 1e-3) / 1e9
-    log("MLUPS %.1f, step kernel %.4f ms, %.0f GB/s algorithmic, tile %s" % (
-        mlups, kernel_ms, achieved, S.snowlb_tile_name(sim.tile)))
+    log("MLUPS %.1f (median of %d), step kernel %.4f ms, %.0f GB/s algorithmic, tile %s; repeats %s" % (
+        mlups, REPEATS, kernel_ms, achieved, S.snowlb_tile_name(sim.tile), reps))
     if diag["status"] != S.OK:
         raise SystemExit("non-finite state after the timed steps")
 
@@ -350,7 +371,11 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "kernel": "k_step", "bytes_per_update": bpu,
+                     "impl_bytes_per_update": impl_bytes_per_update(flow, args.storage),
                      "kernel_avg_ms": round(kernel_ms, 5)},
+        "timing": {"repeats": REPEATS, "statistic": "median", "path": "captured HIP graphs",
+                   "wall_s": reps["wall_s"], "kernel_ms_per_step": reps["kernel_ms"],
+                   "diag_sync_ms": reps["diag_ms"]},
     }
     del sim
     torch.cuda.empty_cache()
@@ -365,12 +390,16 @@ def main():
         for st in ("fp16", "bf16"):
             if st == args.storage or st not in wanted:
                 continue
-            s2, w2, k2, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
+            s2, w2, k2, _, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
             b2 = bytes_per_update(flow, st)
+            i2 = impl_bytes_per_update(flow, st)
             extras["%s_storage" % st] = {"MLUPS": round(cells * min(args.steps, 1000) / w2 / 1e6, 1),
                                          "kernel_avg_ms": round(k2, 5),
                                          "GBps_algorithmic": round(cells * b2 / (k2 * 1e-3) / 1e9, 1),
-                                         "bytes_per_update": b2}
+                                         "frac_algorithmic": round(cells * b2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                         "bytes_per_update": b2,
+                                         "impl_bytes_per_update": i2,
+                                         "GBps_impl": round(cells * i2 / (k2 * 1e-3) / 1e9, 1)}
             log("%s storage: %s" % (st, extras["%s_storage" % st]))
             del s2
         if "stencils" in wanted:

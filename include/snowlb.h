@@ -28,7 +28,8 @@
  *   SNOWLB_TUNE_STEPS      steps per timing sample of the autotuner (default 20, even)
  *   SNOWLB_BUFFER_STAGGER  bytes added after each 64 KiB-padded buffer of a lattice so that the
  *                          buffers a tile touches start on different HBM channels (default 2304)
- *   SNOWLB_GRAPH_STEPS     steps per captured graph of snowlb_step (default 32, even)
+ *   SNOWLB_GRAPH_STEPS     steps per captured graph of snowlb_step (default 32, even); fewer steps
+ *                          than that are replayed from a captured two-step graph
  *   SNOWLB_NO_GRAPH        1: launch every step directly instead of replaying graphs
  *   SNOWLB_ADJ_OVERLAP     0: run the adjoint backward pass in serial order on the caller's stream
  *                          (default 1: recompute the next checkpoint interval on a second stream of
@@ -53,9 +54,13 @@ typedef int32_t snowlb_status;
 
 /* internal storage of the populations (the collision arithmetic is FP32 in all cases) */
 #define SNOWLB_STORE_FP32 0
-#define SNOWLB_STORE_FP16 1 /* FP16 deviations d = p/w - m, round-to-nearest-even: m = rho0 for
-                               f, phi(t-1) of the holding cell for h, U(t-1) of the source cell
-                               for g (kept in extra FP32 planes)                                 */
+#define SNOWLB_STORE_FP16 1 /* FP16 deviations d = p/w - m, round-to-nearest-even, from local
+                               references m: for f_q, rho + 3 c_q.j of the cell it streamed from;
+                               for g_q, U (1 + 3 c_q.j) of that cell (U alone without flow); for
+                               h_q, phi(t-1) of the cell that holds it.  Each cell's U, rho, jx, jy,
+                               rounded to the same 16-bit format, are kept in 16-bit reference
+                               planes inside the population buffer, so writer and reader use the
+                               same rounded values.  phi_prev stays FP32.                        */
 #define SNOWLB_STORE_BF16 2 /* BF16 deviations, same encoding                                   */
 
 /* closure in x (y is always periodic) */
@@ -133,9 +138,12 @@ snowlb_status snowlb_create(const snowlb_params* p, snowlb_ctx** out);
 /* Release a context (NULL-safe).  Synchronises the device first. */
 void snowlb_destroy(snowlb_ctx* ctx);
 
-/* Initial state: a circular tanh seed (phi0 = tanh((R - r)/(sqrt 2 width))), phi_prev = phi0,
- * equilibrium populations at U_init (ny x nx device field) or at params.U0 when U_init_dev is NULL,
- * velocity (1 - phi0)/2 (u_in, 0) for a ventilated domain and 0 otherwise.  Resets the step count. */
+/* Initial state (the circular seed of radius R of Sec. 3.1.2 and Sec. 3.2.2 in uniform
+ * supersaturation): phi0 = tanh((R - r)/(sqrt 2 width)) around (seed_x, seed_y), phi_prev = phi0,
+ * h_q = w_q phi0, equilibrium populations g = g_eq(U, u0) of Sec. 2.2.2 at U = U_init (ny x nx device
+ * field, caller-owned, read before the call's work completes) or at params.U0 when U_init_dev is
+ * NULL, f = f_eq(rho0, u0) of Sec. 2.2.1 with the projected velocity u0 = (1 - phi0)/2 (u_in, 0) for a
+ * ventilated domain and 0 otherwise.  Resets the step count.  EINVAL for a NULL ctx. */
 snowlb_status snowlb_init(snowlb_ctx* ctx, const float* U_init_dev, void* stream);
 
 /* Advance n >= 0 steps (asynchronous).  With diag_every > 0 the host synchronises every diag_every
@@ -144,7 +152,11 @@ snowlb_status snowlb_step(snowlb_ctx* ctx, int32_t n, void* stream);
 int64_t snowlb_step_count(const snowlb_ctx* ctx);
 
 /* Write one macroscopic field (SNOWLB_FIELD_*) of the current state into dst_dev (float,
- * dst_elems >= nx*ny, caller-owned). */
+ * dst_elems >= nx*ny, caller-owned, ny x nx, x fastest): the moments of the populations, phi = sum h
+ * (Sec. 2.2.3), U = sum g (Sec. 2.2.2), rho = sum f, and the velocity of Sec. 2.2.1 that the
+ * collisions use, u = (1 - phi)/2 j/(rho + k/2) (the momentum after the half-force drag correction,
+ * then the projection; 0 without flow).  EINVAL for an unknown field or a short buffer, ESTATE before
+ * the state is initialised. */
 snowlb_status snowlb_read(snowlb_ctx* ctx, int32_t field, float* dst_dev, int64_t dst_elems,
                           void* stream);
 
@@ -163,9 +175,16 @@ snowlb_status snowlb_read_populations(snowlb_ctx* ctx, int32_t set, float* dst_d
 snowlb_status snowlb_write_populations(snowlb_ctx* ctx, int32_t set, const float* src_dev,
                                        int64_t elems, void* stream);
 
-/* FP64 diagnostics of the current state, synchronous (waits for `stream`):
- * out[0..7] = sum rho, sum jx, sum jy, sum U, sum phi, sum phi_prev, #(phi > 0), #non-finite cells.
- * Sums are reduced in a fixed order (deterministic).  Returns ENONFINITE if out[7] > 0. */
+/* FP64 conservation diagnostics of the current state, synchronous (waits for `stream`); out_host
+ * holds SNOWLB_DIAG_COUNT doubles:
+ *   out[0..7] = sum rho, sum jx, sum jy, sum U, sum phi, sum phi_prev, #(phi > 0), #non-finite cells;
+ *   out[8]    = the species invariant sum U + (L_sat/2) sum phi_prev.
+ * Mass and momentum are the moments of the flow populations (Sec. 2.2.1); the invariant follows from
+ * the depletion source -w (L_sat/2) d(phi)/dt of Sec. 2.2.2 taken as phi(t) - phi(t-1): the vapour
+ * lost by a collision is (L_sat/2) times the phase gained, so out[8] is constant in a periodic
+ * domain.  Sums are reduced in FP64 in a fixed order (deterministic).  Returns ENONFINITE if
+ * out[7] > 0 (out is filled), EINVAL for NULL arguments, ESTATE before the state is initialised. */
+#define SNOWLB_DIAG_COUNT 9
 snowlb_status snowlb_diag(snowlb_ctx* ctx, double* out_host, void* stream);
 
 /* Checkpoint / resume: the whole state (populations, phi_prev) and the step count, as an opaque
@@ -227,7 +246,7 @@ snowlb_status snowlb_batch_init(snowlb_batch* b, void* stream);
  * autotunes the tile shape and grid mode for the whole batch. */
 snowlb_status snowlb_batch_step(snowlb_batch* b, int32_t n, void* stream);
 int64_t snowlb_batch_step_count(const snowlb_batch* b);
-/* Field / diagnostics of domain i, as snowlb_read / snowlb_diag. */
+/* Field / diagnostics of domain i, as snowlb_read / snowlb_diag (out_host: SNOWLB_DIAG_COUNT doubles). */
 snowlb_status snowlb_batch_read(snowlb_batch* b, int32_t i, int32_t field, float* dst_dev, int64_t dst_elems,
                                 void* stream);
 snowlb_status snowlb_batch_diag(snowlb_batch* b, int32_t i, double* out_host, void* stream);

@@ -66,8 +66,11 @@ struct Driver {
     int par = 0;
     int64_t step = 0;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int g_steps = 0, g_tile = -1, g_mode = -1;
+    // captured step loops: [0] K steps, [1] two steps (the remainder below K), each starting from copy 0
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        int steps = 0, tile = -1, mode = -1;
+    } graphs[2];
     std::string err;
 
     ~Driver() { release(); }
@@ -98,10 +101,10 @@ struct Driver {
     }
 
     void drop_graph() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        gexec = nullptr;
-        g_steps = 0;
-        g_tile = g_mode = -1;
+        for (StepGraph& g : graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            g = StepGraph{};
+        }
     }
 
     snowlb_status ensure_tiles(int cfg) {
@@ -141,8 +144,13 @@ struct Driver {
         return SNOWLB_OK;
     }
 
-    snowlb_status build_graph(int K) {
-        drop_graph();
+    // Capture K steps (K even, starting from copy 0) into graph slot `which`, unless it already holds
+    // them for the current tile configuration and grid mode.
+    snowlb_status ensure_graph(int which, int K) {
+        StepGraph& G = graphs[which];
+        if (G.exec && G.steps == K && G.tile == tile && G.mode == grid_mode) return SNOWLB_OK;
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        G = StepGraph{};
         const int grid = step_grid(tile, ntiles[tile], storage, flow, inout, rad, grid_mode);
         hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "hipStreamBeginCapture");
@@ -157,39 +165,46 @@ struct Driver {
             return hipfail(le, "step kernel capture");
         }
         if (ee != hipSuccess) return hipfail(ee, "hipStreamEndCapture");
-        hipError_t ie = hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0);
+        hipGraphExec_t ex = nullptr;
+        hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
-        if (ie != hipSuccess) {
-            gexec = nullptr;
-            return hipfail(ie, "hipGraphInstantiate");
-        }
-        g_steps = K;
-        g_tile = tile;
-        g_mode = grid_mode;
+        if (ie != hipSuccess) return hipfail(ie, "hipGraphInstantiate");
+        G.exec = ex;
+        G.steps = K;
+        G.tile = tile;
+        G.mode = grid_mode;
         return SNOWLB_OK;
     }
 
-    // n steps with the current configuration: whole graphs of K steps (K even, starting from copy
-    // 0) while at least K remain, single launches otherwise.
+    snowlb_status replay(int which, int K, hipStream_t s) {
+        hipError_t e = hipGraphLaunch(graphs[which].exec, s);
+        if (e != hipSuccess) return hipfail(e, "hipGraphLaunch");
+        step += K;
+        return SNOWLB_OK;
+    }
+
+    // n steps with the current configuration, replayed from captured graphs: one single launch first
+    // if the state sits in copy 1 (the graphs start from copy 0), then whole graphs of K steps while
+    // at least K remain, then graphs of two steps, and a single launch for an odd last step.
     snowlb_status run(int n, hipStream_t s) {
         snowlb_status st = ensure_tiles(tile);
         if (st) return st;
         const int K = std::max(2, env_int("SNOWLB_GRAPH_STEPS", 32) & ~1);
-        if (n < K || env_int("SNOWLB_NO_GRAPH", 0)) return plain(tile, grid_mode, n, s);
-        if (par == 1) {
+        if (env_int("SNOWLB_NO_GRAPH", 0)) return plain(tile, grid_mode, n, s);
+        if (par == 1 && n > 0) {
             st = plain(tile, grid_mode, 1, s);
             if (st) return st;
             n -= 1;
         }
-        if (n >= K && (!gexec || g_tile != tile || g_mode != grid_mode || g_steps != K)) {
-            st = build_graph(K);
-            if (st) return st;
+        if (n >= K) {
+            if ((st = ensure_graph(0, K))) return st;
+            for (; n >= K; n -= K)
+                if ((st = replay(0, K, s))) return st;
         }
-        while (n >= K) {
-            hipError_t e = hipGraphLaunch(gexec, s);
-            if (e != hipSuccess) return hipfail(e, "hipGraphLaunch");
-            step += K;
-            n -= K;
+        if (n >= 2) {
+            if ((st = ensure_graph(1, 2))) return st;
+            for (; n >= 2; n -= 2)
+                if ((st = replay(1, 2, s))) return st;
         }
         return plain(tile, grid_mode, n, s);
     }
@@ -577,6 +592,7 @@ snowlb_status ctx_diag(snowlb_ctx* c, int par, double* out, hipStream_t s) {
     HIPCHK(c, hipMemcpyAsync(c->h_out, c->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     std::memcpy(out, c->h_out, 8 * sizeof(double));
+    out[8] = out[3] + 0.5 * c->p.L_sat * out[5];  // species invariant: sum U + (L_sat/2) sum phi_prev
     if (out[7] > 0) return fail(c, SNOWLB_ENONFINITE, "non-finite populations found");
     return SNOWLB_OK;
 }
@@ -766,7 +782,7 @@ snowlb_status snowlb_step(snowlb_ctx* c, int32_t n, void* stream) {
         snowlb_status st = from_driver(c, c->drv.run(k, s));
         if (st) return st;
         n -= k;
-        double out[8];
+        double out[SNOWLB_DIAG_COUNT];
         st = ctx_diag(c, c->drv.par, out, s);
         if (st) return st;
     }
@@ -877,6 +893,8 @@ snowlb_status snowlb_set_eps(snowlb_ctx* c, double eps) {
     if (!std::isfinite(eps) || eps < 0 || eps >= 0.5) return fail(c, SNOWLB_EINVAL, "eps must lie in [0, 0.5)");
     c->p.eps = eps;
     fill_dom_physics_eps(c);
+    // steps already queued on any stream read the descriptor: let them finish with the old value
+    HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
     return SNOWLB_OK;
 }
@@ -1049,8 +1067,11 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     }
     const int st = c->adj.stride, n = c->adj.n;
     const int per_area = std::max(st - 1, 1);
-    if (c->adj.nsegdoms != 2 * per_area) {
-        // step i of a recompute in area `ar` reads slot i of the area and writes slot i + 1
+    {
+        // Step i of a recompute in area `ar` reads slot i of the area and writes slot i + 1.  The
+        // descriptors are rebuilt on every call from the context's current domain (eps may have
+        // changed since the forward pass through snowlb_set_eps) and the current slot layout (the
+        // segment areas follow the checkpoints, so they move when the checkpoint count changes).
         std::vector<DomDesc> h((size_t)(2 * per_area), c->dom);
         for (int ar = 0; ar < 2; ++ar)
             for (int i = 0; i + 1 < st; ++i) {
@@ -1062,11 +1083,17 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
                 d.phip[0] = (float*)(a + c->pop_bytes);
                 d.phip[1] = (float*)(b + c->pop_bytes);
             }
-        if (c->adj.d_segdoms) (void)hipFree(c->adj.d_segdoms);
-        c->adj.d_segdoms = nullptr;
-        HIPCHK(c, hipMalloc(&c->adj.d_segdoms, h.size() * sizeof(DomDesc)));
+        if (c->adj.nsegdoms < (int)h.size()) {
+            if (c->adj.d_segdoms) (void)hipFree(c->adj.d_segdoms);
+            c->adj.d_segdoms = nullptr;
+            c->adj.nsegdoms = 0;
+            HIPCHK(c, hipMalloc(&c->adj.d_segdoms, h.size() * sizeof(DomDesc)));
+            c->adj.nsegdoms = (int)h.size();
+        }
+        // the previous backward pass returned only after all of its work (both streams) was done,
+        // so once the caller's stream has drained nothing reads the descriptors any more
+        HIPCHK(c, hipStreamSynchronize(s));
         HIPCHK(c, hipMemcpy(c->adj.d_segdoms, h.data(), h.size() * sizeof(DomDesc), hipMemcpyHostToDevice));
-        c->adj.nsegdoms = (int)h.size();
     }
     float* lam[2] = {c->adj.buf, c->adj.buf + (kAdjPlanes + 1) * cells};
     A.epart = c->adj.epart;

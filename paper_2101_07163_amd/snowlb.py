@@ -178,8 +178,12 @@ def snowlb_write_field(ctx, field: int, src_dev: int, elems: int, stream: int) -
     _check(lib().snowlb_write_field(ctx, field, src_dev, elems, stream), ctx)
 
 
+DIAG_COUNT = 9
+DIAG_KEYS = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite", "species")
+
+
 def snowlb_diag(ctx, stream: int) -> tuple[int, list]:
-    out = (ctypes.c_double * 8)()
+    out = (ctypes.c_double * DIAG_COUNT)()
     s = lib().snowlb_diag(ctx, out, stream)
     if s not in (OK, ENONFINITE):
         _check(s, ctx)
@@ -277,7 +281,7 @@ def snowlb_batch_read(b, i: int, field: int, dst_dev: int, elems: int, stream: i
 
 
 def snowlb_batch_diag(b, i: int, stream: int) -> tuple[int, list]:
-    out = (ctypes.c_double * 8)()
+    out = (ctypes.c_double * DIAG_COUNT)()
     s = lib().snowlb_batch_diag(b, i, out, stream)
     if s not in (OK, ENONFINITE):
         _check(s, batch=b)
@@ -396,9 +400,7 @@ class Sim:
 
     def diag(self) -> dict:
         s, v = snowlb_diag(self.ctx, self.stream)
-        keys = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite")
-        d = dict(zip(keys, v))
-        d["species"] = d["U"] + 0.5 * self.p.L_sat * d["phi_prev"]
+        d = dict(zip(DIAG_KEYS, v))
         d["status"] = s
         return d
 
@@ -478,8 +480,7 @@ class Batch:
 
     def diag(self, i: int) -> dict:
         s, v = snowlb_batch_diag(self.b, i, self.stream)
-        keys = ("rho", "jx", "jy", "U", "phi", "phi_prev", "n_solid", "n_nonfinite")
-        d = dict(zip(keys, v))
+        d = dict(zip(DIAG_KEYS, v))
         d["status"] = s
         return d
 

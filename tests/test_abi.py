@@ -136,3 +136,12 @@ def test_lattice_size_limit():
     p = S.snowlb_params_default()
     p.nx, p.ny = 65537, 8
     assert S.snowlb_validate(p)[0] == S.EINVAL
+
+
+def test_diagnostics_count_matches_header():
+    """snowlb_diag fills SNOWLB_DIAG_COUNT doubles (the eight sums and the species invariant); the
+    binding's buffer has exactly that many."""
+    txt = open(os.path.join(ROOT, "include", "snowlb.h")).read()
+    m = re.search(r"#define\s+SNOWLB_DIAG_COUNT\s+(\d+)", txt)
+    assert m and int(m.group(1)) == S.DIAG_COUNT == len(S.DIAG_KEYS) == 9
+    assert S.DIAG_KEYS[8] == "species"

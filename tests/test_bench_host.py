@@ -26,12 +26,16 @@ def test_more_than_one_gpu_is_refused_with_a_message(argv, env):
 
 
 def test_bytes_per_update():
-    # 23 (flow) or 14 populations read and written, phi_prev read and written (FP32), and for 16-bit
-    # storage the 16-bit references (U, and rho, jx, jy with flow) read and written
+    # algorithmic: 23 (flow) or 14 populations read and written, phi_prev read and written (FP32)
     assert bench.bytes_per_update(True, "fp32") == 23 * 4 * 2 + 8 == 192
     assert bench.bytes_per_update(False, "fp32") == 14 * 4 * 2 + 8 == 120
-    assert bench.bytes_per_update(True, "fp16") == 23 * 2 * 2 + 8 + 4 * 2 * 2 == 116
-    assert bench.bytes_per_update(False, "bf16") == 14 * 2 * 2 + 8 + 1 * 2 * 2 == 68
+    assert bench.bytes_per_update(True, "fp16") == 23 * 2 * 2 + 8 == 100
+    assert bench.bytes_per_update(False, "bf16") == 14 * 2 * 2 + 8 == 64
+    # this implementation's 16-bit storage also reads and writes the 16-bit references (U, and rho,
+    # jx, jy with flow)
+    assert bench.impl_bytes_per_update(True, "fp32") == 192
+    assert bench.impl_bytes_per_update(True, "fp16") == 100 + 4 * 2 * 2 == 116
+    assert bench.impl_bytes_per_update(False, "bf16") == 64 + 1 * 2 * 2 == 68
 
 
 @pytest.fixture

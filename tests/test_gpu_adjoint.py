@@ -215,3 +215,34 @@ def test_c5_full_size_gradients_against_finite_differences():
         L, de, fd_eps, rel(de, fd_eps), du0, fd_U0, rel(du0, fd_U0)))
     assert rel(de, fd_eps) < 1e-3
     assert rel(du0, fd_U0) < 1e-3
+
+
+def _adjoint_on(sim, cfg, U, target, steps, stride):
+    """Forward and backward on an existing context (the optimisation-loop use: one Sim, eps set anew
+    before each forward)."""
+    S.snowlb_set_eps(sim.ctx, cfg["eps"])
+    sim.init(torch.from_numpy(U).float())
+    S.snowlb_adj_forward(sim.ctx, steps, stride, sim.stream)
+    seed = (2 * (sim.read("phi").double() - torch.from_numpy(target).cuda())).float().contiguous()
+    dU = torch.empty_like(seed)
+    de, du0 = S.snowlb_adj_backward(sim.ctx, seed.data_ptr(), dU.data_ptr(), sim.stream)
+    return dU.double().cpu().numpy(), de, du0
+
+
+@pytest.mark.parametrize("overlap", ["0", "1"])
+def test_adjoint_reused_context_matches_fresh_context(overlap, monkeypatch):
+    """One context reused across calls must give bitwise the gradients of a fresh context: after a
+    change of eps between a backward and the next forward (the recompute steps must see the new eps),
+    and after a forward with fewer checkpoints at the same stride (100 -> 90 steps at stride 10: the
+    segment areas that follow the checkpoints move)."""
+    monkeypatch.setenv("SNOWLB_ADJ_OVERLAP", overlap)
+    cfg, p, U, target = setup(48, 100)
+    sim = S.Sim(cfg)
+    _adjoint_on(sim, dict(cfg, eps=0.04), U, target, 100, 10)
+    for eps, steps in ((0.05, 100), (0.05, 90), (0.03, 90)):
+        c2 = dict(cfg, eps=eps)
+        got = _adjoint_on(sim, c2, U, target, steps, 10)
+        ref = _adjoint_on(S.Sim(c2), c2, U, target, steps, 10)
+        print("  eps %.2f n %d: deps %.9e / %.9e" % (eps, steps, got[1], ref[1]))
+        assert got[1] == ref[1] and got[2] == ref[2]
+        assert np.array_equal(got[0], ref[0])

@@ -275,10 +275,12 @@ def test_graph_replay_matches_plain_launches(storage):
     b = S.Sim(cfg, storage=storage).init()
     os.environ["SNOWLB_NO_GRAPH"] = "1"
     try:
-        a.step(69)
+        a.step(69).step(21)
     finally:
         del os.environ["SNOWLB_NO_GRAPH"]
-    b.step(69)  # 1 + 2 x 32 (graph) + 4
+    b.step(69)  # 2 x 32 (K-step graph) + 2 x 2 (two-step graph) + 1 single launch
+    b.step(21)  # from copy 1: 1 single launch + 10 x 2 (two-step graph)
+    assert b.step_count == 90
     sa, sb = gpu_state(a, 1), gpu_state(b, 1)
     for k in sa:
         assert np.array_equal(sa[k], sb[k]), k
@@ -310,6 +312,8 @@ def test_fp64_diagnostics_match_host_sums():
     cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])[:, None, None]
     want = {"rho": f.sum(), "jx": (cx * f).sum(), "jy": (cy * f).sum(), "U": g.sum(), "phi": h.sum(),
             "phi_prev": st["phip"].sum()}
+    # the species invariant of the depletion source (Sec. 2.2.2), returned by the library
+    want["species"] = g.sum() + 0.5 * cfg["L_sat"] * st["phip"].sum()
     for k, v in want.items():
         assert abs(d[k] - v) <= 1e-12 * max(1.0, abs(v)), k
     assert d["n_solid"] == float((h.sum(axis=0) > 0).sum())
