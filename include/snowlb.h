@@ -187,6 +187,19 @@ snowlb_status snowlb_write_populations(snowlb_ctx* ctx, int32_t set, const float
 #define SNOWLB_DIAG_COUNT 9
 snowlb_status snowlb_diag(snowlb_ctx* ctx, double* out_host, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the diagnostics of snowlb_diag, bitwise the same values, written
+ * asynchronously on `stream` to out_dev (SNOWLB_DIAG_COUNT doubles of caller-owned device memory)
+ * without waiting for the stream and without allocating anything.  The per-workgroup partial sums
+ * go to a static device array of the library (2048 x 8 doubles = 128 KiB, one copy per GPU, held until
+ * the process ends); every call on a GPU shares that array, so calls that overlap on one GPU (on
+ * concurrent streams) race, and their results are undefined.  Nothing in the array needs to start at
+ * zero: each call writes every partial it reads.  The partial count is at most 2048 for any lattice
+ * (larger lattices sum more cells per thread); a larger demand would return EINVAL.  Non-finite
+ * cells are counted in out_dev[7]; the call itself returns OK.  EINVAL for NULL arguments, ESTATE
+ * before the state is initialised. */
+snowlb_status snowlb_diag_noalloc(snowlb_ctx* ctx, double* out_dev, void* stream);
+
 /* Checkpoint / resume: the whole state (populations, phi_prev) and the step count, as an opaque
  * device buffer of snowlb_state_bytes() bytes.  load_state requires a buffer saved from a context
  * with identical sizes and storage. */

@@ -380,7 +380,7 @@ struct snowlb_ctx {
     bool local_ref = false;  // 16-bit storage: reference planes exist
     double* d_partials = nullptr;
     double* d_out = nullptr;
-    double* h_out = nullptr;       // pinned, 8 doubles
+    double* h_out = nullptr;       // pinned, SNOWLB_DIAG_COUNT doubles
     StateHeader* h_hdr = nullptr;  // pinned
     Driver drv;
     bool inited = false;
@@ -522,8 +522,8 @@ snowlb_status ctx_alloc(snowlb_ctx* c) {
     HIPCHK(c, hipMalloc(&c->d_dom, sizeof(DomDesc)));
     HIPCHK(c, hipMemcpy(c->d_dom, &c->dom, sizeof(DomDesc), hipMemcpyHostToDevice));
     HIPCHK(c, hipMalloc(&c->d_partials, (size_t)diag_blocks(c->dom) * 8 * sizeof(double)));
-    HIPCHK(c, hipMalloc(&c->d_out, 8 * sizeof(double)));
-    HIPCHK(c, hipHostMalloc(&c->h_out, 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(c, hipMalloc(&c->d_out, SNOWLB_DIAG_COUNT * sizeof(double)));
+    HIPCHK(c, hipHostMalloc(&c->h_out, SNOWLB_DIAG_COUNT * sizeof(double), hipHostMallocDefault));
     HIPCHK(c, hipHostMalloc(&c->h_hdr, sizeof(StateHeader), hipHostMallocDefault));
     return SNOWLB_OK;
 }
@@ -587,12 +587,11 @@ snowlb_status ctx_init(snowlb_ctx* c, const float* U_init, hipStream_t s) {
 }
 
 snowlb_status ctx_diag(snowlb_ctx* c, int par, double* out, hipStream_t s) {
-    hipError_t e = launch_diag(c->dom, par, c->d_partials, c->d_out, s);
+    hipError_t e = launch_diag(c->dom, par, c->d_partials, c->d_out, 0.5 * c->p.L_sat, s);
     if (e != hipSuccess) return hip_fail(c, e, "diag kernels");
-    HIPCHK(c, hipMemcpyAsync(c->h_out, c->d_out, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(c->h_out, c->d_out, SNOWLB_DIAG_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    std::memcpy(out, c->h_out, 8 * sizeof(double));
-    out[8] = out[3] + 0.5 * c->p.L_sat * out[5];  // species invariant: sum U + (L_sat/2) sum phi_prev
+    std::memcpy(out, c->h_out, SNOWLB_DIAG_COUNT * sizeof(double));
     if (out[7] > 0) return fail(c, SNOWLB_ENONFINITE, "non-finite populations found");
     return SNOWLB_OK;
 }
@@ -840,6 +839,19 @@ snowlb_status snowlb_diag(snowlb_ctx* c, double* out, void* stream) {
     if (!c || !out) return fail(c, SNOWLB_EINVAL, "NULL argument");
     if (!c->inited) return fail(c, SNOWLB_ESTATE, "diag before init");
     return ctx_diag(c, c->drv.par, out, (hipStream_t)stream);
+}
+
+snowlb_status snowlb_diag_noalloc(snowlb_ctx* c, double* out_dev, void* stream) {
+    if (!c || !out_dev) return fail(c, SNOWLB_EINVAL, "NULL argument");
+    if (!c->inited) return fail(c, SNOWLB_ESTATE, "diag before init");
+    if (diag_blocks(c->dom) > kDiagMaxBlocks)
+        return fail(c, SNOWLB_EINVAL, "diagnostics need more partials than the static scratch holds");
+    double* scr = nullptr;  // this device's copy of the static scratch array
+    hipError_t e = diag_scratch(&scr);
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    e = launch_diag(c->dom, c->drv.par, scr, out_dev, 0.5 * c->p.L_sat, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(c, e, "diag kernels");
+    return SNOWLB_OK;
 }
 
 int64_t snowlb_state_bytes(const snowlb_ctx* c) { return c ? ctx_state_bytes(c) : -1; }

@@ -115,10 +115,14 @@ hipError_t launch_read(const DomDesc& d, int par, int field, float* dst, hipStre
 hipError_t launch_write_field(const DomDesc& d, int par, int field, const float* src, hipStream_t s);
 hipError_t launch_pop_io(const DomDesc& d, int par, int set, int to_canonical, float* canon,
                          hipStream_t s);
-// FP64 diagnostics: partials (nblk x 8 doubles) then out[8]; returns the number of blocks used via
-// diag_blocks().
+// FP64 diagnostics: partials (diag_blocks() x 8 doubles, at most kDiagMaxBlocks x 8) then out[9]:
+// the eight sums and the species invariant sum U + half_Lsat sum phi_prev.
+constexpr int kDiagMaxBlocks = 2048;
 int diag_blocks(const DomDesc& d);
-hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out, hipStream_t s);
+hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s);
+// Device address, on the current device, of the diagnostics' static scratch array (kDiagMaxBlocks x 8
+// doubles), looked up on the first call per device.
+hipError_t diag_scratch(double** out);
 
 hipError_t launch_copy(void* dst, const void* src, int64_t bytes, hipStream_t s);
 

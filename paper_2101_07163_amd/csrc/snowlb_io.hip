@@ -3,6 +3,8 @@
 // layout, FP64 diagnostics and a plain copy that measures the practical HBM ceiling.  None of them is
 // on the per-step path; they favour plain per-cell code over speed.
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stdint.h>
 
 #include "snowlb_device.h"
@@ -389,8 +391,34 @@ static constexpr int kDiagThreads = 256;
 int diag_blocks(const DomDesc& d) {
     const long cells = (long)d.nx * d.ny;
     long b = (cells + kDiagThreads * 4 - 1) / (kDiagThreads * 4);
-    if (b > 2048) b = 2048;
+    if (b > kDiagMaxBlocks) b = kDiagMaxBlocks;  // larger lattices loop over more cells per thread
     return (int)(b < 1 ? 1 : b);
+}
+
+// Scratch of the allocation-free diagnostics (snowlb_diag_noalloc): the per-workgroup partials, at
+// most kDiagMaxBlocks x 8 doubles (128 KiB), in a file-scope device array.  Each GPU the library
+// runs on holds its own copy until the process ends; host code never passes the array's name to a
+// kernel (on the host it is only a stand-in), but the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device and kept.
+static __device__ __align__(256) double scratch[kDiagMaxBlocks * 8];
+
+hipError_t diag_scratch(double** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = p;
+    }
+    *out = static_cast<double*>(ptr[dev]);
+    return hipSuccess;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -451,10 +479,14 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag(DomDesc d, int par, doubl
     }
 }
 
-__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ partials, int nblk, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ partials, int nblk, double half_Lsat,
+                                                    double* __restrict__ out) {
     // 32 lanes per quantity: lane l of quantity k sums blocks l, l + 32, ... in order, then lane 0
-    // adds the 32 lane sums in order.  Fixed order, hence deterministic.
+    // adds the 32 lane sums in order.  Fixed order, hence deterministic.  Then the species invariant
+    // sum U + (L_sat/2) sum phi_prev (the vapour the depletion source of Sec. 2.2.2 removes is
+    // (L_sat/2) times the phase gained).
     __shared__ double s[8][32];
+    __shared__ double tot[8];
     const int k = threadIdx.x / 32, l = threadIdx.x % 32;
     double v = 0;
     for (int b = l; b < nblk; b += 32) v += partials[(int64_t)b * 8 + k];
@@ -464,22 +496,25 @@ __global__ void __launch_bounds__(256) k_diag_final(const double* __restrict__ p
         double t = 0;
         for (int i = 0; i < 32; ++i) t += s[k][i];
         out[k] = t;
+        tot[k] = t;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) out[8] = __dadd_rn(tot[3], __dmul_rn(half_Lsat, tot[5]));
 }
 
 template <class S>
-static hipError_t diag_s(const DomDesc& d, int par, double* partials, double* out, hipStream_t s) {
+static hipError_t diag_s(const DomDesc& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s) {
     const int nb = diag_blocks(d);
     hipLaunchKernelGGL(k_diag<S>, dim3(nb), dim3(kDiagThreads), 0, s, d, par, partials);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, partials, nb, out);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, partials, nb, half_Lsat, out);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out, hipStream_t s) {
+hipError_t launch_diag(const DomDesc& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s) {
     switch (d.storage) {
-        case 0: return diag_s<StoreF32>(d, par, partials, out, s);
-        case 1: return diag_s<StoreF16>(d, par, partials, out, s);
-        case 2: return diag_s<StoreBF16>(d, par, partials, out, s);
+        case 0: return diag_s<StoreF32>(d, par, partials, out, half_Lsat, s);
+        case 1: return diag_s<StoreF16>(d, par, partials, out, half_Lsat, s);
+        case 2: return diag_s<StoreBF16>(d, par, partials, out, half_Lsat, s);
     }
     return hipErrorInvalidValue;
 }

@@ -66,6 +66,7 @@ _SIGS = {
     "snowlb_write_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
     "snowlb_write_field": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
     "snowlb_diag": (ctypes.c_int32, [_v, _P(ctypes.c_double), _v]),
+    "snowlb_diag_noalloc": (ctypes.c_int32, [_v, _v, _v]),
     "snowlb_state_bytes": (ctypes.c_int64, [_v]),
     "snowlb_save_state": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
     "snowlb_load_state": (ctypes.c_int32, [_v, _v, ctypes.c_int64, _v]),
@@ -188,6 +189,10 @@ def snowlb_diag(ctx, stream: int) -> tuple[int, list]:
     if s not in (OK, ENONFINITE):
         _check(s, ctx)
     return s, list(out)
+
+
+def snowlb_diag_noalloc(ctx, out_dev: int, stream: int) -> None:
+    _check(lib().snowlb_diag_noalloc(ctx, out_dev, stream), ctx)
 
 
 def snowlb_state_bytes(ctx) -> int:
