@@ -1,0 +1,174 @@
+"""Writes how far the FP64 oracle's own phase field moves under noise of FP32 size, for the long
+ventilated runs, and the oracle's fields of every member of the 64-crystal sweep:
+
+    python tests/golden/make_oracle_spread.py v512 c2 c4 c3
+
+For each case the oracle runs twice from the same initial state: as is, and with every population and
+phi_prev multiplied by (1 + sigma sqrt(k) xi) every k = 10 steps, xi ~ N(0, 1) (a seeded draw), sigma =
+2^-23 per step: one FP32 unit in the last place per value and step, about what the few roundings a
+step applies to each stored value add up to.  The spread is the largest |phi_noisy - phi| over the
+compared region at each checkpoint.  A FP32 run of the same case cannot be expected closer to the
+oracle than this spread where it exceeds the 1e-4 target; the GPU tests bound their error by
+max(1e-4, 2 x spread).
+
+Cases (regions are the cells the GPU tests compare):
+  v512  the 2048^2 workload's physics on 512^2 (seed (150, 256)), 10^4 steps, whole lattice
+  c2    the 1024^2 workload over 2*10^4 steps, the stored crop rows [256, 768) x columns [44, 556)
+  c3    the 2048^2 workload over 10^4 steps, the stored crop (reference: c3_crop_10000.npz)
+  c4    each of the 64 crystals over 5000 steps, the box around its crystal (phi > -0.9, widened by
+        16 cells); also stores each crystal's phi and U on that box (float32) in c4_members_5000.npz
+
+Results go to oracle_spread.json (merged with what is there).  It calls only the oracle; c4 and c3
+take about an hour each on 8 cores.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2101_07163_amd import workloads as W  # noqa: E402  (the workloads' parameters)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+JSON = os.path.join(HERE, "oracle_spread.json")
+C4_NPZ = os.path.join(HERE, "c4_members_5000.npz")
+SIGMA = 2.0 ** -23  # relative noise per value and step
+EVERY = 10
+
+
+def v512_cfg():
+    cfg = dict(W.C3)
+    cfg.update(nx=512, ny=512, seed=(150.0, 256.0, 8.0))
+    return cfg
+
+
+def new(cfg):
+    return oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
+
+
+def perturb(o, rng, k):
+    s = o.get_state()
+    a = SIGMA * np.sqrt(k)
+    for name in ("f", "g", "h", "phip"):
+        if name == "f" and not o.p.flow:
+            s[name] = None
+            continue
+        s[name] = s[name] * (1.0 + a * rng.standard_normal(s[name].shape))
+    o.set_state(**s)
+
+
+def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
+    """phi spread at each checkpoint over region ((r0, r1), (c0, c1)); the reference runs alongside
+    unless its phi on the region at the last checkpoint is given (ref_at_end)."""
+    (r0, r1), (c0, c1) = region
+    rng = np.random.default_rng(seed)
+    noisy = new(cfg)
+    ref = None if ref_at_end is not None else new(cfg)
+    out = {}
+    done, t0 = 0, time.time()
+    while done < steps:
+        k = min(EVERY, steps - done)
+        noisy.step(k)
+        if ref is not None:
+            ref.step(k)
+        done += k
+        perturb(noisy, rng, k)
+        if done in checkpoints:
+            a = noisy.fields()["phi"][r0:r1, c0:c1]
+            b = ref.fields()["phi"][r0:r1, c0:c1] if ref is not None else ref_at_end
+            out[str(done)] = float(np.abs(a - b).max())
+            print("%s step %d spread %.3e (%.0f s)" % (log, done, out[str(done)], time.time() - t0), flush=True)
+    return out
+
+
+def load():
+    return json.load(open(JSON)) if os.path.exists(JSON) else {}
+
+
+def save(d):
+    with open(JSON + ".tmp", "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(JSON + ".tmp", JSON)
+
+
+def header():
+    return {"sigma_per_step": SIGMA, "every": EVERY, "noise": "relative, N(0, 1), seeded"}
+
+
+def case_v512():
+    cfg = v512_cfg()
+    d = dict(header(), region=[[0, 512], [0, 512]],
+             spread_phi=spread_run(cfg, 10000, {2500, 5000, 10000}, ((0, 512), (0, 512)), 512, log="v512"))
+    return d
+
+
+def case_c2():
+    region = ((256, 768), (44, 556))
+    return dict(header(), region=[list(region[0]), list(region[1])],
+                spread_phi=spread_run(W.C2, 20000, {5000, 10000, 15000, 20000}, region, 1024, log="c2"))
+
+
+def case_c3():
+    data = np.load(os.path.join(HERE, "c3_crop_10000.npz"))
+    (r0, r1), (c0, c1) = W.C3["crop"]
+    ref = data["phi"].astype(np.float64)
+    return dict(header(), region=[[r0, r1], [c0, c1]], reference="c3_crop_10000.npz (float32)",
+                spread_phi=spread_run(W.C3, 10000, {10000}, ((r0, r1), (c0, c1)), 2048, ref_at_end=ref, log="c3"))
+
+
+def crystal_box(phi, pad=16):
+    ys, xs = np.nonzero(phi > -0.9)
+    ny, nx = phi.shape
+    return ((max(0, int(ys.min()) - pad), min(ny, int(ys.max()) + 1 + pad)),
+            (max(0, int(xs.min()) - pad), min(nx, int(xs.max()) + 1 + pad)))
+
+
+def case_c4():
+    cfgs = W.c4_domains()
+    steps = cfgs[0]["steps"]
+    arrays, members = {}, []
+    if os.path.exists(C4_NPZ):  # resume
+        old = np.load(C4_NPZ)
+        arrays = {k: old[k] for k in old.files}
+        members = load().get("c4", {}).get("members", [])
+    t0 = time.time()
+    for i in range(len(members), len(cfgs)):
+        cfg = cfgs[i]
+        ref = new(cfg).step(steps)
+        F = ref.fields()
+        (r0, r1), (c0, c1) = crystal_box(F["phi"])
+        arrays["phi_%d" % i] = F["phi"][r0:r1, c0:c1].astype(np.float32)
+        arrays["U_%d" % i] = F["U"][r0:r1, c0:c1].astype(np.float32)
+        arrays["box_%d" % i] = np.array([r0, r1, c0, c1], dtype=np.int64)
+        sp = spread_run(cfg, steps, {steps}, ((r0, r1), (c0, c1)), 7163 + i,
+                        ref_at_end=F["phi"][r0:r1, c0:c1], log="c4[%d] %dx%d" % (i, cfg["nx"], cfg["ny"]))
+        members.append({"i": i, "nx": cfg["nx"], "eps": cfg["eps"], "U0": cfg["U0"], "u_in": cfg["u_in"],
+                        "box": [[r0, r1], [c0, c1]], "spread_phi": sp[str(steps)]})
+        np.savez_compressed(C4_NPZ + ".tmp.npz", steps=np.int64(steps), **{k: v for k, v in arrays.items() if k != "steps"})
+        os.replace(C4_NPZ + ".tmp.npz", C4_NPZ)
+        d = load()
+        d["c4"] = dict(header(), steps=steps, members=members)
+        save(d)
+        print("c4 member %d done (%.0f s)" % (i, time.time() - t0), flush=True)
+    return load()["c4"]
+
+
+CASES = {"v512": case_v512, "c2": case_c2, "c3": case_c3, "c4": case_c4}
+
+
+def main(names):
+    for n in names:
+        r = CASES[n]()
+        d = load()
+        d[n] = r
+        save(d)
+        print("wrote", JSON, n, flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:] or ["v512"])

@@ -30,3 +30,19 @@ def test_stored_crop_matches_its_recipe(name):
     assert (phi > 0).sum() > 100  # a grown crystal inside the crop
     assert abs(float(d["rho"].mean()) - cfg["rho0"]) < 1e-2
     assert 0.0 < float(d["ux"].max()) < 0.1  # inflow-driven, low Mach
+
+
+def test_stored_adjoint_matches_its_recipe():
+    """The oracle's discrete adjoint of the 512^2 adjoint workload (tests/golden/make_oracle_adjoint.py):
+    shapes, the run length, a grown target shape, and the identity dL/dU0 = sum dL/dU_init."""
+    import make_oracle_adjoint as A
+    from paper_2101_07163_amd import workloads as W
+    d = np.load(A.OUT)
+    cfg = W.C5
+    assert int(d["steps"]) == cfg["steps"]
+    assert d["target"].shape == (cfg["ny"], cfg["nx"]) and d["target"].dtype == np.float64
+    assert d["dU"].shape == (cfg["ny"], cfg["nx"]) and d["dU"].dtype == np.float32
+    assert np.isfinite(d["dU"]).all() and np.isfinite(d["target"]).all()
+    assert (d["target"] > 0).sum() > 1000  # the target crystal grew well beyond the seed
+    assert float(d["L"]) > 0
+    assert abs(float(d["dU"].astype(np.float64).sum()) / float(d["dU0"]) - 1) < 1e-6

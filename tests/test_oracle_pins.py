@@ -664,3 +664,131 @@ def test_paper_numbers():
     assert abs(si.lattice_velocity(0.24, 4.8e-6, 2e-7) - 0.01) < 1e-15
     assert abs(si.lattice_velocity(0.12, 4.8e-6, 2e-7) - 0.005) < 1e-15
     assert abs(si.lattice_viscosity(1.152e-6, 4.8e-6, 2e-7) - 0.01) < 1e-12
+
+
+# ------------------------------------------------------------------ branches the one-step and long-run
+# parity tests cannot pin (both sides share the reading): the ventilated initial state, the outlet
+# closure, and the velocity read-out and momentum coupling of a non-uniform partial solid
+
+def test_ventilated_initial_state_moments():
+    """Initial state of a ventilated domain (reading R10): at every cell the populations are the
+    equilibria of Sec. 2.2.1 and 2.2.2 at the projected inflow velocity u0 = (1 - phi0)/2 (u_in, 0),
+    so their moments are fixed whatever the equilibria's form: sum f = rho0, sum c f = rho0 u0,
+    sum c c f = rho0 (I/3 + u0 u0); sum g = U, sum c g = U u0; sum h = phi0 with phi_prev = phi0.  The
+    seed profile is the tanh of reading R10: phi0 = 0 on the nodes at distance R from the centre, and
+    atanh(phi0) is affine in the distance with slope -1/(sqrt 2 w).  Sums over the lattice to 1e-13."""
+    nx, ny, R, w, rho0, u_in, U0 = 48, 40, 10.0, 1.3, 1.03, 0.017, 0.55
+    xs, ys = 20.0, 17.0
+    p = oracle.Params(nx=nx, ny=ny, flow=1, inout=1, u_in=u_in, U_in=U0, rho0=rho0)
+    rng = np.random.default_rng(3)
+    U = U0 + 0.05 * rng.standard_normal((ny, nx))
+    o = oracle.Oracle(p).init_seed(xs, ys, R, w, U0, U)
+    st = o.get_state()
+    f, g, h, phip = st["f"], st["g"], st["h"], st["phip"]
+    phi0 = h.sum(axis=0)
+    assert np.array_equal(phip, phi0) or np.abs(phip - phi0).max() < 1e-15
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    r = np.hypot(xx - xs, yy - ys)
+    on_circle = np.abs(r - R) < 1e-12  # (30, 17), (26, 25), ...: integer nodes at distance 10
+    assert on_circle.sum() >= 8 and np.abs(phi0[on_circle]).max() < 1e-15
+    inner = np.abs(phi0) < 0.999
+    slope, icpt = np.polyfit(r[inner], np.arctanh(phi0[inner]), 1)
+    assert abs(slope + 1 / (math.sqrt(2) * w)) < 1e-12 and abs(icpt - R / (math.sqrt(2) * w)) < 1e-11
+    s = 0.5 * (1 - phi0)
+    u0x = s * u_in
+    cx, cy = CX[:, None, None], CY[:, None, None]
+    N = nx * ny
+    assert abs(f.sum() - rho0 * N) < 1e-13 * N
+    assert abs((cx * f).sum() - rho0 * u_in * s.sum()) < 1e-13 * N
+    assert abs((cy * f).sum()) < 1e-13 * N
+    assert np.abs((cx * cx * f).sum(axis=0) - rho0 * (1 / 3 + u0x ** 2)).max() < 1e-15
+    assert np.abs((cx * cy * f).sum(axis=0)).max() < 1e-15
+    assert abs(g.sum() - U.sum()) < 1e-13 * N
+    assert abs((cx[:5] * g).sum() - u_in * (U * s).sum()) < 1e-13 * N
+    assert np.abs((cx[:5] * g).sum(axis=0) - U * u0x).max() < 1e-15
+    assert abs((cy[:5] * g).sum()) < 1e-13 * N
+
+
+def test_outlet_closure_against_erfc_front():
+    """The zero-gradient outlet (reading R9) on a step of U advected by a uniform inflow through the
+    outlet, no crystal (phi = -1, diffusivity D = (tau_vap - 1/2)/3): the solution on the infinite
+    line is U = U_b + (U_a - U_b)/2 erfc((x - x_f - u t)/(2 sqrt(D t))).  While the front crosses the
+    outlet (front at column 159.5 of 0..159), the closure may only add the boundary layer of a
+    Neumann outflow: at the last column no more than the first-order estimate (D/u) |dU/dx| of the
+    front's slope, decaying monotonically inwards, and nothing beyond the bulk discretisation error
+    (2e-3 of the step) 15 columns in.  After the front has passed, the state relaxes to U_a again.
+    A reflecting, periodic or zeroing closure misses these bars by far."""
+    nx, ny, u, tau_v = 160, 4, 0.05, 0.8
+    D = (tau_v - 0.5) / 3
+    Ua, Ub, x0 = 0.7, 0.5, 40.0
+    p = oracle.Params(nx=nx, ny=ny, flow=1, inout=1, u_in=u, U_in=Ua, rho0=1.0, tau_vap=tau_v)
+    o = oracle.Oracle(p)
+    x = np.arange(nx, dtype=float)
+    o.init_seed(0.0, 0.0, -1000.0, 1.0, 0.0, np.where(x < x0, Ua, Ub)[None, :] * np.ones((ny, 1)))
+    from scipy.special import erfc
+    for t, at_outlet in ((1000, False), (2400, True), (3000, True), (6000, False)):
+        o.step(t - o.step_count)
+        U = o.fields()["U"]
+        assert np.abs(U - U[0]).max() < 1e-13  # uniform in y
+        xf = x0 - 0.5 + u * t
+        ex = Ub + (Ua - Ub) / 2 * erfc((x - xf) / (2 * math.sqrt(D * t)))
+        err = np.abs(U[0] - ex) / (Ua - Ub)
+        assert err[: nx - 15].max() < 2e-3, (t, err[: nx - 15].max())
+        if at_outlet:
+            slope = math.exp(-((nx - 1 - xf) ** 2) / (4 * D * t)) / (2 * math.sqrt(math.pi * D * t))
+            assert err[-1] <= 1.2 * (D / u) * slope, (t, err[-1], (D / u) * slope)
+            assert np.all(np.diff(err[-6:]) > 0)  # a boundary layer, not a reflected wave
+        else:
+            assert err.max() < 2e-3, (t, err.max())
+
+
+def _mush_state(n, seed):
+    """A periodic state with a non-uniform partial solid: phi in (-1, 1) varying smoothly, density and
+    momentum varying from cell to cell."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.mgrid[0:n, 0:n]
+    phi = 0.9 * np.sin(2 * np.pi * xx / n + 0.3) * np.cos(2 * np.pi * yy / n)
+    rho = 1.0 + 0.02 * np.cos(2 * np.pi * (xx + 2 * yy) / n)
+    ux = 0.02 * np.sin(2 * np.pi * yy / n)
+    uy = -0.015 * np.cos(2 * np.pi * xx / n)
+    f = np.stack([oracle.feq(rho[j, i], ux[j, i], uy[j, i]) for j in range(n) for i in range(n)], axis=1)
+    f = f.reshape(9, n, n) * (1 + 0.01 * rng.standard_normal((9, n, n)))
+    h = W9()[:, None, None] * phi[None] * (1 + 0.02 * rng.standard_normal((9, n, n)))
+    return f, h
+
+
+def test_velocity_readout_and_momentum_coupling_in_a_non_uniform_mush():
+    """Velocity read-out and drag of a non-uniform partial solid (Sec. 2.2.1, reading R4).  At every
+    cell the read-out u must satisfy the defining relation of the half-force velocity under the
+    projection, rho u / s = j - (k/2) u / s with s = (1 - phi)/2 and k = h nu (1 + phi)^2 (1 - phi)/(4 W0^2)
+    (phi clamped to [-1, 1]), i.e. rho u + (k/2) u - s j = 0 -- checked as a residual, not through the
+    solved formula; u = 0 in full ice and u = j/rho in pure fluid.  One step of a periodic box then
+    changes the total momentum by the sum over cells of the first moment of the Guo-forced
+    collision, -(j - rho u)/tau_f + (1 - 1/(2 tau_f)) F with F = -k u (streaming moves momentum
+    between cells without changing the total), to 1e-13."""
+    n, tau, hd, W0 = 24, 1.5, 2.757, 0.5  # a strong drag: k up to about 1 in the mush
+    p = oracle.Params(nx=n, ny=n, flow=1, tau_f=tau, h_drag=hd, W0=W0)
+    f, h = _mush_state(n, 11)
+    o = oracle.Oracle(p).set_state(f=f, g=np.zeros((5, n, n)), h=h, phip=h.sum(axis=0))
+    F = o.fields()
+    cx, cy = CX[:, None, None], CY[:, None, None]
+    rho, jx, jy, phi = f.sum(axis=0), (cx * f).sum(axis=0), (cy * f).sum(axis=0), h.sum(axis=0)
+    assert np.abs(F["phi"] - phi).max() < 1e-14 and np.abs(F["rho"] - rho).max() < 1e-14
+    pc = np.clip(phi, -1, 1)
+    s = 0.5 * (1 - pc)
+    k = hd * (tau - 0.5) / 3 * (1 + pc) ** 2 * (1 - pc) / (4 * W0 * W0)
+    for u, j in ((F["ux"], jx), (F["uy"], jy)):
+        assert np.abs(rho * u + 0.5 * k * u - s * j).max() < 1e-16
+    assert np.abs(F["ux"]).max() > 1e-3 and k.max() > 0.5  # a real mush, not the limits
+    o.step(1)
+    f1 = o.get_state()["f"]
+    for u, j, c in ((F["ux"], jx, cx), (F["uy"], jy, cy)):
+        want = j.sum() + (-(j - rho * u) / tau + (1 - 0.5 / tau) * (-k * u)).sum()
+        assert abs((c * f1).sum() - want) < 1e-13, ((c * f1).sum(), want)
+    # the limits: pure fluid keeps u = j / rho, full ice is at rest
+    for phi_c, check in ((-1.0, lambda u, j: np.abs(u - j / rho).max() < 1e-16),
+                         (1.0, lambda u, j: np.abs(u).max() == 0.0)):
+        o2 = oracle.Oracle(p).set_state(f=f, g=np.zeros((5, n, n)), h=_uniform_phase(n, n, phi_c),
+                                        phip=phi_c * np.ones((n, n)))
+        F2 = o2.fields()
+        assert check(F2["ux"], jx) and check(F2["uy"], jy)
