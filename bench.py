@@ -278,6 +278,38 @@ def adjoint_ratio(S, torch, W):
             "plain_forward_MLUPS": round(cells * n / (plain_ms * 1e-3) / 1e6, 1)}
 
 
+def three_d(S, torch, W, steps=200, warmup=20):
+    """The 3D extension on its workload (256 x 128 x 128 ventilated crystal, FP32): MLUPS and the
+    step kernel's algorithmic bandwidth, (19 + 7 + 7) populations x 4 B read and written plus phi_prev
+    read and written = 272 B per cell update."""
+    cfg = W.F4_3D
+    sim = S.Sim3D(cfg).init()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    walls, kms = [], []
+    for _ in range(REPEATS):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        kms.append(e0.elapsed_time(e1) / steps)
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    bpu = (19 + 7 + 7) * 4 * 2 + 8
+    k_ms = float(np.median(kms))
+    gbs = cells * bpu / (k_ms * 1e-3) / 1e9
+    d = sim.diag()
+    del sim
+    return {"workload": cfg["name"], "steps": steps, "MLUPS": round(cells * steps / float(np.median(walls)) / 1e6, 1),
+            "kernel_avg_ms": round(k_ms, 5), "bytes_per_update": bpu, "GBps_algorithmic": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "finite": d["status"] == S.OK}
+
+
 def cpu_baseline(cfg, seconds, threads=0):
     """The FP64 oracle timed on a bounded sample of the workload (whole steps of the full lattice from
     the seeded initial state), on all host threads or on `threads` of them."""
@@ -315,9 +347,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5,stencils,table2",
+    ap.add_argument("--extras", default="copy,fp16,bf16,c4,c5,stencils,table2,f4",
                     help="comma list of extra measurements: copy (copy-kernel ceiling), fp16, bf16, "
-                         "c4 (64-crystal batch), c5 (adjoint/forward time ratio)")
+                         "c4 (64-crystal batch), c5 (adjoint/forward time ratio), stencils, table2 (habit "
+                         "sweep), f4 (the 3D extension)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -414,6 +447,9 @@ def main():
         if "c5" in wanted:
             extras["c5_adjoint"] = adjoint_ratio(S, torch, W)
             log("adjoint: %s" % extras["c5_adjoint"])
+        if "f4" in wanted:
+            extras["f4_3d"] = three_d(S, torch, W)
+            log("3D extension: %s" % extras["f4_3d"])
         out["extras"] = extras
 
     if not args.no_cpu_baseline:

@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIB_DIR, "libsnowlb.so")
-SOURCES = [os.path.join(HERE, "csrc", s) for s in ("snowlb_kernels.hip", "snowlb_io.hip", "snowlb_adjoint.hip", "snowlb_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", s) for s in ("snowlb_kernels.hip", "snowlb_io.hip", "snowlb_adjoint.hip",
+                                                    "snowlb_api.cpp", "snowlb3d_kernels.hip", "snowlb3d_api.cpp")]
 ARCH = os.environ.get("SNOWLB_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU instructions (the scalar and

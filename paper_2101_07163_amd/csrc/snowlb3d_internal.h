@@ -1,0 +1,51 @@
+// snowlb3d_internal.h -- descriptors shared by the 3D kernels and the 3D host runtime of libsnowlb.
+//
+// Device layout (per lattice): one buffer per copy holds the populations (f_0..f_18 with flow, g_0..g_6,
+// h_0..h_6: npop planes) in blocks of 16 x 4 x 4 cells with the block's planes side by side; phi_prev
+// (one FP32 plane) has a buffer of its own in the same cell order.  Two copies of each ping-pong.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snowlb3d {
+
+constexpr int kBX = 16, kBY = 4, kBZ = 4, kBlockCells = kBX * kBY * kBZ;
+
+// Element (q, x, y, z) of a buffer of nq planes sits at
+//     ((z / 4) nby nbx + (y / 4) nbx + x / 16) nq 256  +  256 q  +  64 (z % 4) + 16 (y % 4) + x % 16,
+// the sum of an x, a y and a z part.  The host keeps every byte offset inside a buffer below 2^32.
+__host__ __device__ __forceinline__ uint32_t xpart(int x, int nq) {
+    return (uint32_t)(x >> 4) * ((uint32_t)nq << 8) + (uint32_t)(x & 15);
+}
+__host__ __device__ __forceinline__ uint32_t ypart(int y, int nbx, int nq) {
+    return (uint32_t)(y >> 2) * (((uint32_t)nbx * (uint32_t)nq) << 8) + ((uint32_t)(y & 3) << 4);
+}
+__host__ __device__ __forceinline__ uint32_t zpart(int z, int nbx, int nby, int nq) {
+    return (uint32_t)(z >> 2) * (((uint32_t)nbx * (uint32_t)nby * (uint32_t)nq) << 8) + ((uint32_t)(z & 3) << 6);
+}
+
+struct Dom3 {
+    int32_t nx, ny, nz, nbx, nby, nbz, npop, flow, inout, pad0;
+    float* pop[2];   // the two population copies
+    float* phip[2];  // phi(t-1), one plane each
+    double grad_eps2;
+    float eps, Dphi, coefN, inv_tau0, lam, half_Lsat, tauv_m_half, omega_f, guo, kdrag, rho0, u_in, U_in;
+    float df_in[19];  // inlet ghost f_eq(rho0, (u_in, 0, 0)) - w
+    float g_in[7];    // inlet ghost g_eq(U_in, (u_in, 0, 0))
+    float pad1;
+};
+
+// One step of every block of the lattice, reading copy par and writing copy 1 - par.
+hipError_t launch_step3(const Dom3& d, const Dom3* d_dev, int par, hipStream_t s);
+hipError_t launch_init3(const Dom3& d, int par, const float* U_init, float U0, float sx, float sy, float sz,
+                        float R, float width, hipStream_t s);
+// field: 0 phi, 1 U, 2 rho, 3 ux, 4 uy, 5 uz -> dst [z][y][x]
+hipError_t launch_read3(const Dom3& d, int par, int field, float* dst, hipStream_t s);
+// set: 0 f (19), 1 g (7), 2 h (7), 3 phi_prev; canonical [q][z][y][x] FP32
+hipError_t launch_pop_io3(const Dom3& d, int par, int set, int to_canonical, float* canon, hipStream_t s);
+// FP64 diagnostics: partials (diag_blocks3() x 9 doubles) then out[10] (the 9 sums, then the species
+// invariant sum U + half_Lsat sum phi_prev)
+int diag_blocks3(const Dom3& d);
+hipError_t launch_diag3(const Dom3& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s);
+
+}  // namespace snowlb3d

@@ -1,0 +1,540 @@
+// snowlb3d_kernels.hip -- gfx950 kernels of the coupled lattice-Boltzmann ice-growth step in three
+// dimensions, the extension of the 2D method (Tan et al., arXiv:2101.07163, Sec. 2.2) that its Sec. 4
+// proposes.  Lattices: D3Q19 flow, D3Q7 vapour and phase field (cs^2 = 1/4); gradient over the 18
+// D3Q19 neighbours with weights 1/6 (axes) and 1/12 (face diagonals); hexagonal anisotropy about the
+// z (c) axis, a = 1 + eps Re((n_x + i n_y)^6), which is the paper's 1 + eps cos 6 theta for normals in
+// the basal plane; x periodic or inlet/outlet, y and z periodic.
+//
+// k_step3 is one fused step per 16 x 4 x 4 block of cells, built like the 2D k_step: the block's h
+// and phi (FP64) are staged with a one-cell halo in LDS (the gradient and the destination term
+// h_q(x + c_q, t) of Eq. (d)), each cell collides all three populations and pushes them to their
+// destinations, and every (destination, q) is written by exactly one thread.  FP32 storage; the
+// collisions close their zeroth and first moments through FP64 sums, as in 2D.
+#include <hip/hip_runtime.h>
+
+#include "snowlb3d_internal.h"
+
+namespace snowlb3d {
+
+#define GMEM __attribute__((address_space(1)))
+
+// D3Q19: rest, 6 axis, 12 face diagonals; D3Q7 is the first seven
+__device__ constexpr int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__device__ constexpr float W19[19] = {1.f / 3.f,  1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
+                                      1.f / 18.f, 1.f / 18.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                                      1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
+                                      1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+__device__ constexpr float W7[7] = {0.25f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    if (i < 0) i += n;
+    if (i >= n) i -= n;
+    if ((unsigned)i >= (unsigned)n) i = ((i % n) + n) % n;
+    return i;
+}
+
+// Closure of a lattice position: y, z periodic; x periodic or (inlet/outlet) the inlet ghost left of
+// x = 0 (returns false) and a copy of plane nx - 1 right of it.
+template <bool INOUT>
+__device__ __forceinline__ bool map3(const Dom3& d, int gx, int gy, int gz, int& sx, int& sy, int& sz) {
+    sy = wrapi(gy, d.ny);
+    sz = wrapi(gz, d.nz);
+    if (INOUT) {
+        if (gx < 0) {
+            sx = 0;
+            return false;
+        }
+        sx = gx < d.nx ? gx : d.nx - 1;
+    } else {
+        sx = wrapi(gx, d.nx);
+    }
+    return true;
+}
+
+template <class T>
+__device__ __forceinline__ T gld(const GMEM char* base, uint32_t boff) {
+    asm("" : "+s"(base));
+    return *(const GMEM T*)(base + boff);
+}
+template <class T>
+__device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
+    asm("" : "+s"(base));
+    *(GMEM T*)(base + boff) = v;
+}
+
+template <bool FLOW, bool INOUT>
+__global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ dp, int par, int xcd_remap) {
+    constexpr int LX = kBX + 2, LY = kBY + 2, LZ = kBZ + 2, LN = LX * LY * LZ;
+    constexpr int NP = FLOW ? 33 : 14;                       // planes per block of a copy
+    constexpr int PF = 0, PG = FLOW ? 19 : 0, PH = PG + 7;  // first plane of f, g and h
+    constexpr uint32_t PB = kBlockCells * 4;                 // bytes between the planes of a block
+    __shared__ double s_phi[LN];
+    __shared__ float s_h[7][LN];
+    const Dom3& d = *dp;
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = (tid >> 4) & 3, tz = tid >> 6;
+    // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid)
+    const int G = gridDim.x, b = blockIdx.x;
+    const int t = xcd_remap ? (b % 8) * (G / 8) + min(b % 8, G % 8) + b / 8 : b;
+    const int bx = t % d.nbx, by = (t / d.nbx) % d.nby, bz = t / (d.nbx * d.nby);
+    const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    const bool active = x < d.nx && y < d.ny && z < d.nz;
+    const int par1 = 1 - par;
+    const GMEM char* pin = (const GMEM char*)d.pop[par];
+    GMEM char* pout = (GMEM char*)d.pop[par1];
+    const GMEM char* phin = (const GMEM char*)d.phip[par];
+    GMEM char* phout = (GMEM char*)d.phip[par1];
+
+    const uint32_t xp = xpart(x, NP), yp = ypart(y, d.nbx, NP), zp = zpart(z, d.nbx, d.nby, NP);
+    const uint32_t co = xp + yp + zp;
+    const uint32_t cf = xpart(x, 1) + ypart(y, d.nbx, 1) + zpart(z, d.nbx, d.nby, 1);
+
+    // the cell's own flow, vapour and phi_prev first, then the halo box of h
+    float f[19], g[7], phip = 0.f;
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) g[q] = gld<float>(pin + (PG + q) * PB, co * 4);
+        if (FLOW) {
+#pragma unroll
+            for (int q = 0; q < 19; ++q) f[q] = gld<float>(pin + (PF + q) * PB, co * 4);
+        }
+        phip = gld<float>(phin, cf * 4);
+    }
+    for (int p = tid; p < LN; p += kBlockCells) {
+        const int lx = p % LX, ly = (p / LX) % LY, lz = p / (LX * LY);
+        int sx, sy, sz;
+        const bool real = map3<INOUT>(d, x0 + lx - 1, y0 + ly - 1, z0 + lz - 1, sx, sy, sz);
+        double p64 = -1.0;  // inlet ghost: phi = -1 (its h are never read)
+        float hh[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (real) {
+            const uint32_t o = xpart(sx, NP) + ypart(sy, d.nbx, NP) + zpart(sz, d.nbx, d.nby, NP);
+            p64 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) {
+                hh[q] = gld<float>(pin + (PH + q) * PB, o * 4);
+                p64 += (double)hh[q];
+            }
+        }
+        s_phi[p] = p64;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) s_h[q][p] = hh[q];
+    }
+    __syncthreads();
+    if (!active) return;  // no barrier follows
+
+    const int own = ((tz + 1) * LY + (ty + 1)) * LX + (tx + 1);
+    float h[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) h[q] = s_h[q][own];
+    const double phi64 = s_phi[own];
+    const float phi = (float)phi64;
+
+    // isotropic gradient over the 18 D3Q19 neighbours, FP64
+    double gx64 = 0.0, gy64 = 0.0, gz64 = 0.0;
+#pragma unroll
+    for (int q = 1; q < 19; ++q) {
+        const double w = q < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
+        const double v = w * s_phi[own + (CZ[q] * LY + CY[q]) * LX + CX[q]];
+        gx64 += CX[q] * v;
+        gy64 += CY[q] * v;
+        gz64 += CZ[q] * v;
+    }
+    // anisotropy a = 1 + eps P, P = Re((n_x + i n_y)^6), and the flux N = kappa Dphi |g|^2 a da/dg:
+    // with X = gx^2/|g|^2, Y = gy^2/|g|^2,  P = X^3 - 15 X^2 Y + 15 X Y^2 - Y^3 and
+    // |g|^2 dP/dg = 6 (gx (X^2 - 10 X Y + 5 Y^2 - P), -gy (5 X^2 - 10 X Y + Y^2 + P), -gz P)
+    float a = 1.f, Nx = 0.f, Ny = 0.f, Nz = 0.f;
+    if (gx64 * gx64 + gy64 * gy64 + gz64 * gz64 > d.grad_eps2) {
+        const float gx = (float)gx64, gy = (float)gy64, gz = (float)gz64;
+        const float inv = 1.f / (gx * gx + gy * gy + gz * gz);
+        const float X = gx * gx * inv, Y = gy * gy * inv;
+        const float P = X * X * X - 15.f * X * X * Y + 15.f * X * Y * Y - Y * Y * Y;
+        a = 1.f + d.eps * P;
+        const float c = d.coefN * a;  // coefN = 6 kappa_N eps W0^2/tau0
+        Nx = c * gx * (X * X - 10.f * X * Y + 5.f * Y * Y - P);
+        Ny = -c * gy * (5.f * X * X - 10.f * X * Y + Y * Y + P);
+        Nz = -c * gz * P;
+    }
+    const float a2 = a * a;
+    const float ia2 = 1.f / a2;
+    const float B = ia2 - 1.f;
+    const float ieta = 1.f / (4.f * d.Dphi * a2 + 0.5f);
+    const float om = 1.f - phi * phi;
+
+    // vapour: U as an FP64 sum (exact for a few FP32 values)
+    const double U64 = (((double)g[0] + (double)g[1]) + ((double)g[2] + (double)g[3])) +
+                       (((double)g[4] + (double)g[5]) + (double)g[6]);
+    const float U = (float)U64;
+    const float srcQ = (phi - phi * phi * phi + d.lam * U * om * om) * d.inv_tau0;
+
+    // flow: deviations df = f - w, FP64 moments, Guo forcing, moments of the collision closed in FP64
+    float ux = 0.f, uy = 0.f, uz = 0.f, fs[19];
+    if (FLOW) {
+        double m64 = 0.0, jx64 = 0.0, jy64 = 0.0, jz64 = 0.0;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            m64 += (double)f[q];
+            jx64 += CX[q] * (double)f[q];
+            jy64 += CY[q] * (double)f[q];
+            jz64 += CZ[q] * (double)f[q];
+        }
+        const float drho = (float)m64, rho = 1.f + drho;
+        const float pc = fminf(fmaxf(phi, -1.f), 1.f);
+        const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
+        const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
+        ux = (float)jx64 * sc;
+        uy = (float)jy64 * sc;
+        uz = (float)jz64 * sc;
+        const float Fx = -k * ux, Fy = -k * uy, Fz = -k * uz;
+        const float uu = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
+        float s8 = 0.f, sS = 0.f, feq[19], Sg[19];
+#pragma unroll
+        for (int q = 1; q < 19; ++q) {
+            const float cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
+            const float cF = CX[q] * Fx + CY[q] * Fy + CZ[q] * Fz;
+            feq[q] = W19[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+            Sg[q] = d.guo * W19[q] * (3.f * (cF - uF) + 9.f * cu * cF);
+            s8 += feq[q];
+            sS += Sg[q];
+        }
+        feq[0] = drho - s8;
+        Sg[0] = -sS;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
+        // after collision the first moments are j - omega (j - rho u) + (1 - omega/2) F and the zeroth
+        // is unchanged: fs_1, fs_3, fs_5 (+x, +y, +z) take the first moments as remainders, fs_0 the
+        // zeroth, every sum in FP64
+        const double omd = d.omega_f, gud = d.guo;
+        const double px = jx64 - omd * (jx64 - (double)rho * (double)ux) + gud * (double)Fx;
+        const double py = jy64 - omd * (jy64 - (double)rho * (double)uy) + gud * (double)Fy;
+        const double pz = jz64 - omd * (jz64 - (double)rho * (double)uz) + gud * (double)Fz;
+        // the other populations' shares of each first moment (fs_1, fs_3 and fs_5 carry momentum along
+        // their own axis only, so the three remainders are independent)
+        double rx = 0.0, ry = 0.0, rz = 0.0;
+#pragma unroll
+        for (int q = 2; q < 19; ++q) {
+            if (q != 3 && q != 5) {
+                rx += CX[q] * (double)fs[q];
+                ry += CY[q] * (double)fs[q];
+                rz += CZ[q] * (double)fs[q];
+            } else if (q == 3) {
+                rz += CZ[q] * (double)fs[q];
+            } else {
+                ry += CY[q] * (double)fs[q];
+            }
+        }
+        fs[1] = (float)(px - rx);
+        fs[3] = (float)(py - ry);
+        fs[5] = (float)(pz - rz);
+        double s64 = 0.0;
+#pragma unroll
+        for (int q = 1; q < 19; ++q) s64 += (double)fs[q];
+        fs[0] = (float)(m64 - s64);
+    }
+
+    // vapour collision (D3Q7, cs^2 = 1/4): tau_g = 1/2 + (tau_vap - 1/2) clamp((1 - phi)/2, 0, 1)
+    const float sq = fminf(fmaxf(0.5f * (1.f - phi), 0.f), 1.f);
+    const float itg = 1.f / (0.5f + d.tauv_m_half * sq);
+    const float srcg = d.half_Lsat * (phi - phip);
+    float gs[7];
+    {
+        float geq[7], sg6 = 0.f;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) {
+            geq[q] = W7[q] * U * (1.f + 4.f * (CX[q] * ux + CY[q] * uy + CZ[q] * uz));
+            sg6 += geq[q];
+        }
+        geq[0] = U - sg6;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) gs[q] = g[q] - (g[q] - geq[q]) * itg - W7[q] * srcg;
+        double r64 = 0.0;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) r64 += (double)gs[q];
+        gs[0] = (float)((U64 - (double)srcg) - r64);  // the zeroth moment after collision is U - src
+    }
+
+    // phase field (Eq. (d)/(e) on D3Q7): equilibrium w (phi - c.N/cs^2), source w Q/tau0, rest as
+    // remainder
+    float P7[7];
+    {
+        float heq[7], sh = 0.f, sQ = 0.f;
+#pragma unroll
+        for (int q = 1; q < 7; ++q) {
+            heq[q] = W7[q] * (phi - 4.f * (CX[q] * Nx + CY[q] * Ny + CZ[q] * Nz));
+            sh += heq[q];
+            sQ += W7[q] * srcQ;
+        }
+        heq[0] = phi - sh;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            const float shq = q == 0 ? srcQ - sQ : W7[q] * srcQ;
+            P7[q] = (h[q] - (h[q] - heq[q]) * ieta + shq) * ia2;
+        }
+    }
+
+    // push streaming into copy 1 - par; destinations with the closure
+    const int yN = y + 1 < d.ny ? y + 1 : 0, yS = y > 0 ? y - 1 : d.ny - 1;
+    const int zU = z + 1 < d.nz ? z + 1 : 0, zD = z > 0 ? z - 1 : d.nz - 1;
+    const int xE = x + 1 < d.nx ? x + 1 : (INOUT ? -1 : 0);
+    const int xW = x > 0 ? x - 1 : (INOUT ? -1 : d.nx - 1);
+    const uint32_t xpE = xpart(xE < 0 ? 0 : xE, NP), xpW = xpart(xW < 0 ? 0 : xW, NP);
+    const uint32_t ypN = ypart(yN, d.nbx, NP), ypS = ypart(yS, d.nbx, NP);
+    const uint32_t zpU = zpart(zU, d.nbx, d.nby, NP), zpD = zpart(zD, d.nbx, d.nby, NP);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        if (!FLOW && q >= 7) break;
+        const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
+        const uint32_t xo = CX[q] > 0 ? xpE : (CX[q] < 0 ? xpW : xp);
+        const uint32_t yo = CY[q] > 0 ? ypN : (CY[q] < 0 ? ypS : yp);
+        const uint32_t zo = CZ[q] > 0 ? zpU : (CZ[q] < 0 ? zpD : zp);
+        const int lq = own + (CZ[q] * LY + CY[q]) * LX + CX[q];  // destination in the halo box
+        if (xd >= 0) {
+            const uint32_t dO = (xo + yo + zo) * 4;
+            if (q < 7) {
+                gst<float>(pout + (PH + q) * PB, dO, P7[q] - B * s_h[q][lq]);
+                gst<float>(pout + (PG + q) * PB, dO, gs[q]);
+            }
+            if (FLOW) gst<float>(pout + (PF + q) * PB, dO, fs[q]);
+        }
+        if (INOUT) {
+            if (CX[q] < 0 && x == d.nx - 1) {
+                // the outlet ghost at x = nx copies this plane: it streams into (nx-1, y + cy, z + cz)
+                const uint32_t dO = (xp + yo + zo) * 4;
+                const int ld = own + (CZ[q] * LY + CY[q]) * LX;
+                if (q < 7) {
+                    gst<float>(pout + (PH + q) * PB, dO, P7[q] - B * s_h[q][ld]);
+                    gst<float>(pout + (PG + q) * PB, dO, gs[q]);
+                }
+                gst<float>(pout + (PF + q) * PB, dO, fs[q]);
+            }
+            if (CX[q] > 0 && x == 0) {
+                // the inlet ghost at x = -1: equilibrium (rho0, (u_in, 0, 0); U_in; phi = -1)
+                if (q < 7) {
+                    gst<float>(pout + (PH + q) * PB, co * 4, -W7[q]);
+                    gst<float>(pout + (PG + q) * PB, co * 4, d.g_in[q]);
+                }
+                gst<float>(pout + (PF + q) * PB, co * 4, d.df_in[q]);
+            }
+        }
+    }
+    gst<float>(phout, cf * 4, phi);
+}
+
+template <bool FLOW, bool INOUT>
+static void* step_fn() {
+    return reinterpret_cast<void*>(&k_step3<FLOW, INOUT>);
+}
+
+hipError_t launch_step3(const Dom3& d, const Dom3* d_dev, int par, hipStream_t s) {
+    void* fn = !d.flow ? step_fn<false, false>() : (d.inout ? step_fn<true, true>() : step_fn<true, false>());
+    if (!d.flow && d.inout) return hipErrorInvalidValue;
+    const int grid = d.nbx * d.nby * d.nbz;
+    int remap = 1;
+    void* args[] = {(void*)&d_dev, (void*)&par, (void*)&remap};
+    return hipLaunchKernel(fn, dim3(grid), dim3(kBlockCells), args, 0, s);
+}
+
+// ------------------------------------------------------------------------------------------ set-up
+// and read-out: plain per-cell kernels (not on the per-step path)
+
+__device__ __forceinline__ int64_t idx(const Dom3& d, int nq, int q, int x, int y, int z) {
+    return (int64_t)xpart(x, nq) + ypart(y, d.nbx, nq) + zpart(z, d.nbx, d.nby, nq) + (int64_t)q * kBlockCells;
+}
+
+__global__ void k_init3(Dom3 d, int par, const float* U_init, float U0, float sx, float sy, float sz, float R,
+                        float width) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= d.nx) return;
+    const int NP = d.npop, PG = d.flow ? 19 : 0, PH = PG + 7;
+    const float dx = x - sx, dy = y - sy, dz = z - sz;
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float phi0 = tanhf((R - r) / (1.41421356237309505f * width));
+    const float ux = (d.flow && d.inout) ? 0.5f * (1.f - phi0) * d.u_in : 0.f;
+    const int64_t c = ((int64_t)z * d.ny + y) * d.nx + x;
+    const float U = U_init ? U_init[c] : U0;
+    float* pb = d.pop[par];
+    d.phip[par][idx(d, 1, 0, x, y, z)] = phi0;
+    float s = 0.f;
+    for (int q = 1; q < 7; ++q) {
+        pb[idx(d, NP, PH + q, x, y, z)] = W7[q] * phi0;
+        s += W7[q] * phi0;
+    }
+    pb[idx(d, NP, PH, x, y, z)] = phi0 - s;
+    s = 0.f;
+    for (int q = 1; q < 7; ++q) {
+        const float v = W7[q] * U * (1.f + 4.f * CX[q] * ux);
+        pb[idx(d, NP, PG + q, x, y, z)] = v;
+        s += v;
+    }
+    pb[idx(d, NP, PG, x, y, z)] = U - s;
+    if (d.flow) {
+        const float drho = d.rho0 - 1.f, uu = ux * ux;
+        s = 0.f;
+        for (int q = 1; q < 19; ++q) {
+            const float cu = CX[q] * ux;
+            const float v = W19[q] * (drho + d.rho0 * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+            pb[idx(d, NP, q, x, y, z)] = v;
+            s += v;
+        }
+        pb[idx(d, NP, 0, x, y, z)] = drho - s;
+    }
+}
+
+hipError_t launch_init3(const Dom3& d, int par, const float* U_init, float U0, float sx, float sy, float sz,
+                        float R, float width, hipStream_t s) {
+    hipLaunchKernelGGL(k_init3, dim3((d.nx + 127) / 128, d.ny, d.nz), dim3(128), 0, s, d, par, U_init, U0, sx, sy,
+                       sz, R, width);
+    return hipGetLastError();
+}
+
+// moments of one cell: phi, U, rho and the velocity the collisions use
+__device__ void cell_fields(const Dom3& d, int par, int x, int y, int z, float out[6]) {
+    const int NP = d.npop, PG = d.flow ? 19 : 0, PH = PG + 7;
+    const float* pb = d.pop[par];
+    double phi = 0.0, U = 0.0;
+    for (int q = 0; q < 7; ++q) {
+        phi += pb[idx(d, NP, PH + q, x, y, z)];
+        U += pb[idx(d, NP, PG + q, x, y, z)];
+    }
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    if (d.flow)
+        for (int q = 0; q < 19; ++q) {
+            const double v = pb[idx(d, NP, q, x, y, z)];
+            rho += v;
+            j[0] += CX[q] * v;
+            j[1] += CY[q] * v;
+            j[2] += CZ[q] * v;
+        }
+    out[0] = (float)phi;
+    out[1] = (float)U;
+    out[2] = d.flow ? (float)(1.0 + rho) : 0.f;
+    out[3] = out[4] = out[5] = 0.f;
+    if (d.flow) {
+        const float pc = fminf(fmaxf(out[0], -1.f), 1.f);
+        const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
+        const float sc = 0.5f * (1.f - pc) / (out[2] + 0.5f * k);
+        for (int c = 0; c < 3; ++c) out[3 + c] = (float)j[c] * sc;
+    }
+}
+
+__global__ void k_read3(Dom3 d, int par, int field, float* dst) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= d.nx) return;
+    float v[6];
+    cell_fields(d, par, x, y, z, v);
+    dst[((int64_t)z * d.ny + y) * d.nx + x] = v[field];
+}
+
+hipError_t launch_read3(const Dom3& d, int par, int field, float* dst, hipStream_t s) {
+    if (field < 0 || field > 5) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_read3, dim3((d.nx + 127) / 128, d.ny, d.nz), dim3(128), 0, s, d, par, field, dst);
+    return hipGetLastError();
+}
+
+// canonical FP32 [q][z][y][x] <-> the blocked layout (f is stored as f - w)
+__global__ void k_pop_io3(Dom3 d, int par, int set, int to_canon, float* canon) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= d.nx) return;
+    const int64_t n = (int64_t)d.nx * d.ny * d.nz, c = ((int64_t)z * d.ny + y) * d.nx + x;
+    if (set == 3) {
+        float* p = &d.phip[par][idx(d, 1, 0, x, y, z)];
+        if (to_canon) canon[c] = *p;
+        else *p = canon[c];
+        return;
+    }
+    const int NP = d.npop, PG = d.flow ? 19 : 0, PH = PG + 7;
+    const int nq = set == 0 ? 19 : 7, base = set == 0 ? 0 : (set == 1 ? PG : PH);
+    for (int q = 0; q < nq; ++q) {
+        float* p = &d.pop[par][idx(d, NP, base + q, x, y, z)];
+        const float w = set == 0 ? W19[q] : 0.f;
+        if (to_canon) canon[q * n + c] = *p + w;
+        else *p = canon[q * n + c] - w;
+    }
+}
+
+hipError_t launch_pop_io3(const Dom3& d, int par, int set, int to_canon, float* canon, hipStream_t s) {
+    hipLaunchKernelGGL(k_pop_io3, dim3((d.nx + 127) / 128, d.ny, d.nz), dim3(128), 0, s, d, par, set, to_canon,
+                       canon);
+    return hipGetLastError();
+}
+
+// FP64 diagnostics: per-thread sums over a fixed set of cells, wave64 shuffle, LDS, one partial per
+// workgroup, then one workgroup adds the partials in a fixed order (deterministic)
+constexpr int kDiagThreads = 256, kDiagQ = 9;
+
+int diag_blocks3(const Dom3& d) {
+    const long cells = (long)d.nx * d.ny * d.nz;
+    long b = (cells + kDiagThreads * 4 - 1) / (kDiagThreads * 4);
+    if (b > 2048) b = 2048;
+    return (int)(b < 1 ? 1 : b);
+}
+
+__global__ void __launch_bounds__(kDiagThreads) k_diag3(Dom3 d, int par, double* partials) {
+    const int NP = d.npop, PG = d.flow ? 19 : 0, PH = PG + 7;
+    double acc[kDiagQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int64_t cells = (int64_t)d.nx * d.ny * d.nz;
+    for (int64_t c = (int64_t)blockIdx.x * kDiagThreads + threadIdx.x; c < cells; c += (int64_t)gridDim.x * kDiagThreads) {
+        const int x = (int)(c % d.nx), y = (int)((c / d.nx) % d.ny), z = (int)(c / ((int64_t)d.nx * d.ny));
+        const float* pb = d.pop[par];
+        double phi = 0.0, U = 0.0, rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+        bool bad = false;
+        for (int q = 0; q < 7; ++q) {
+            const float hv = pb[idx(d, NP, PH + q, x, y, z)], gv = pb[idx(d, NP, PG + q, x, y, z)];
+            bad |= !isfinite(hv) || !isfinite(gv);
+            phi += hv;
+            U += gv;
+        }
+        if (d.flow)
+            for (int q = 0; q < 19; ++q) {
+                const float fv = pb[idx(d, NP, q, x, y, z)];
+                bad |= !isfinite(fv);
+                const double v = (double)(W19[q] + fv);  // f as the read-out gives it (FP32 w + (f - w))
+                rho += v;
+                j[0] += CX[q] * v;
+                j[1] += CY[q] * v;
+                j[2] += CZ[q] * v;
+            }
+        const float pp = d.phip[par][idx(d, 1, 0, x, y, z)];
+        bad |= !isfinite(pp);
+        acc[0] += rho; acc[1] += j[0]; acc[2] += j[1]; acc[3] += j[2]; acc[4] += U; acc[5] += phi; acc[6] += pp;
+        acc[7] += phi > 0.0 ? 1.0 : 0.0;
+        acc[8] += bad ? 1.0 : 0.0;
+    }
+    __shared__ double s_part[kDiagThreads / 64][kDiagQ];
+    const int lane = threadIdx.x % 64, wid = threadIdx.x / 64;
+    for (int k = 0; k < kDiagQ; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) s_part[wid][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDiagQ) {
+        double v = 0.0;
+        for (int w = 0; w < kDiagThreads / 64; ++w) v += s_part[w][threadIdx.x];
+        partials[(int64_t)blockIdx.x * kDiagQ + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_diag3_final(const double* partials, int nblk, double half_Lsat, double* out) {
+    if (threadIdx.x != 0) return;
+    double t[kDiagQ];
+    for (int k = 0; k < kDiagQ; ++k) {
+        double v = 0.0;
+        for (int b = 0; b < nblk; ++b) v += partials[(int64_t)b * kDiagQ + k];
+        t[k] = v;
+        out[k] = v;
+    }
+    out[kDiagQ] = __dadd_rn(t[4], __dmul_rn(half_Lsat, t[6]));  // species invariant
+}
+
+hipError_t launch_diag3(const Dom3& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s) {
+    const int nb = diag_blocks3(d);
+    hipLaunchKernelGGL(k_diag3, dim3(nb), dim3(kDiagThreads), 0, s, d, par, partials);
+    hipLaunchKernelGGL(k_diag3_final, dim3(1), dim3(64), 0, s, partials, nb, half_Lsat, out);
+    return hipGetLastError();
+}
+
+}  // namespace snowlb3d

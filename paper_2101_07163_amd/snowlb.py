@@ -46,9 +46,23 @@ class snowlb_params(ctypes.Structure):
     ]
 
 
+class snowlb3d_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("flow", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("W0", ctypes.c_double), ("tau0", ctypes.c_double),
+        ("lam", ctypes.c_double), ("L_sat", ctypes.c_double), ("tau_vap", ctypes.c_double),
+        ("tau_f", ctypes.c_double), ("h_drag", ctypes.c_double), ("kappa_N", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("u_in", ctypes.c_double), ("U_in", ctypes.c_double),
+        ("grad_eps2", ctypes.c_double), ("U0", ctypes.c_double),
+        ("seed_x", ctypes.c_double), ("seed_y", ctypes.c_double), ("seed_z", ctypes.c_double),
+        ("seed_r", ctypes.c_double), ("init_width", ctypes.c_double),
+    ]
+
+
 _lib = None
 
-# exported symbol -> (restype, argtypes); the CPU-only ABI test checks this table against the header
+# exported symbol -> (restype, argtypes); the CPU-only ABI test checks this table against the headers
 _P = ctypes.POINTER
 _v = ctypes.c_void_p
 _SIGS = {
@@ -92,6 +106,19 @@ _SIGS = {
     "snowlb_batch_set_tile": (ctypes.c_int32, [_v, ctypes.c_int32, ctypes.c_int32]),
     "snowlb_batch_get_tile": (ctypes.c_int32, [_v]),
     "snowlb_batch_last_error": (ctypes.c_char_p, [_v]),
+    # three dimensions (include/snowlb3d.h)
+    "snowlb3d_params_default": (None, [_P(snowlb3d_params)]),
+    "snowlb3d_validate": (ctypes.c_int32, [_P(snowlb3d_params), _P(ctypes.c_char_p)]),
+    "snowlb3d_create": (ctypes.c_int32, [_P(snowlb3d_params), _P(_v)]),
+    "snowlb3d_destroy": (None, [_v]),
+    "snowlb3d_last_error": (ctypes.c_char_p, [_v]),
+    "snowlb3d_init": (ctypes.c_int32, [_v, _v, _v]),
+    "snowlb3d_step": (ctypes.c_int32, [_v, ctypes.c_int32, _v]),
+    "snowlb3d_step_count": (ctypes.c_int64, [_v]),
+    "snowlb3d_read": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb3d_read_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb3d_write_populations": (ctypes.c_int32, [_v, ctypes.c_int32, _v, ctypes.c_int64, _v]),
+    "snowlb3d_diag": (ctypes.c_int32, [_v, _P(ctypes.c_double), _v]),
 }
 
 
@@ -118,10 +145,12 @@ def _status_name(s: int) -> str:
         return "status %d" % s
 
 
-def _check(status: int, ctx=None, batch=None):
+def _check(status: int, ctx=None, batch=None, ctx3=False):
     if status != OK:
         if batch is not None:
             msg = lib().snowlb_batch_last_error(batch).decode()
+        elif ctx3:
+            msg = lib().snowlb3d_last_error(ctx).decode()
         else:
             msg = lib().snowlb_last_error(ctx).decode()
         raise SnowlbError(status, msg)
@@ -540,3 +569,156 @@ def snow_adjoint(eps, U_init, sim: Sim, n_steps: int, ckpt_stride: int = 0):
     if _SNOW_ADJOINT is None:
         _SNOW_ADJOINT = _adjoint_function()
     return _SNOW_ADJOINT.apply(eps, U_init, sim, n_steps, ckpt_stride)
+
+
+# ----------------------------------------------------------------------------- three dimensions
+
+FIELDS3 = {"phi": 0, "U": 1, "rho": 2, "ux": 3, "uy": 4, "uz": 5}
+POPS3 = {"f": (POP_F, 19), "g": (POP_G, 7), "h": (POP_H, 7), "phip": (POP_PHIP, 1)}
+DIAG3_KEYS = ("rho", "jx", "jy", "jz", "U", "phi", "phi_prev", "n_solid", "n_nonfinite", "species")
+
+
+def snowlb3d_params_default() -> snowlb3d_params:
+    p = snowlb3d_params()
+    lib().snowlb3d_params_default(ctypes.byref(p))
+    return p
+
+
+def snowlb3d_validate(p: snowlb3d_params) -> tuple[int, str]:
+    msg = ctypes.c_char_p()
+    st = lib().snowlb3d_validate(ctypes.byref(p), ctypes.byref(msg))
+    return st, (msg.value or b"").decode()
+
+
+def snowlb3d_create(p: snowlb3d_params) -> ctypes.c_void_p:
+    ctx = ctypes.c_void_p()
+    _check(lib().snowlb3d_create(ctypes.byref(p), ctypes.byref(ctx)), None, ctx3=True)
+    return ctx
+
+
+def snowlb3d_destroy(ctx) -> None:
+    lib().snowlb3d_destroy(ctx)
+
+
+def snowlb3d_init(ctx, U_init_dev: int | None, stream: int) -> None:
+    _check(lib().snowlb3d_init(ctx, U_init_dev, stream), ctx, ctx3=True)
+
+
+def snowlb3d_step(ctx, n: int, stream: int) -> None:
+    _check(lib().snowlb3d_step(ctx, int(n), stream), ctx, ctx3=True)
+
+
+def snowlb3d_step_count(ctx) -> int:
+    return int(lib().snowlb3d_step_count(ctx))
+
+
+def snowlb3d_read(ctx, field: int, dst_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb3d_read(ctx, field, dst_dev, elems, stream), ctx, ctx3=True)
+
+
+def snowlb3d_read_populations(ctx, pset: int, dst_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb3d_read_populations(ctx, pset, dst_dev, elems, stream), ctx, ctx3=True)
+
+
+def snowlb3d_write_populations(ctx, pset: int, src_dev: int, elems: int, stream: int) -> None:
+    _check(lib().snowlb3d_write_populations(ctx, pset, src_dev, elems, stream), ctx, ctx3=True)
+
+
+def snowlb3d_diag(ctx, stream: int) -> tuple[int, list]:
+    out = (ctypes.c_double * len(DIAG3_KEYS))()
+    st = lib().snowlb3d_diag(ctx, out, stream)
+    if st not in (OK, ENONFINITE):
+        _check(st, ctx, ctx3=True)
+    return st, list(out)
+
+
+def make_params3d(cfg: dict, diag_every: int = 0) -> snowlb3d_params:
+    """snowlb3d_params from a workload dict (keys as in workloads.py, seed = (x, y, z, R))."""
+    p = snowlb3d_params_default()
+    p.nx, p.ny, p.nz = int(cfg["nx"]), int(cfg["ny"]), int(cfg["nz"])
+    p.flow = int(cfg.get("flow", 0))
+    p.bc_x = int(cfg.get("inout", 0))
+    for k in ("eps", "W0", "tau0", "lam", "L_sat", "tau_vap", "tau_f", "h_drag", "kappa_N", "rho0",
+              "u_in", "U_in", "grad_eps2", "U0"):
+        if k in cfg:
+            setattr(p, k, float(cfg[k]))
+    sx, sy, sz, R = cfg.get("seed", (p.nx / 2, p.ny / 2, p.nz / 2, 5.0))
+    p.seed_x, p.seed_y, p.seed_z, p.seed_r = float(sx), float(sy), float(sz), float(R)
+    p.init_width = float(cfg.get("w_init", 1.0))
+    p.diag_every = int(diag_every)
+    return p
+
+
+class Sim3D:
+    """One 3D lattice on the current GPU; buffers in and out are torch CUDA tensors ([z, y, x] fields)."""
+
+    def __init__(self, cfg: dict | snowlb3d_params, diag_every: int = 0):
+        import torch
+        self.torch = torch
+        self.p = cfg if isinstance(cfg, snowlb3d_params) else make_params3d(cfg, diag_every)
+        self.ctx = snowlb3d_create(self.p)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                snowlb3d_destroy(ctx)
+            except Exception:  # interpreter shutdown
+                pass
+            self.ctx = None
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream().cuda_stream
+
+    @property
+    def shape(self):
+        return (self.p.nz, self.p.ny, self.p.nx)
+
+    def init(self, U_init=None):
+        ptr = None
+        if U_init is not None:
+            U_init = self.torch.as_tensor(U_init, dtype=self.torch.float32, device="cuda").contiguous()
+            assert tuple(U_init.shape) == self.shape
+            self._U_init = U_init
+            ptr = U_init.data_ptr()
+        snowlb3d_init(self.ctx, ptr, self.stream)
+        return self
+
+    def step(self, n: int = 1):
+        snowlb3d_step(self.ctx, n, self.stream)
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return snowlb3d_step_count(self.ctx)
+
+    def read(self, field: str):
+        out = self.torch.empty(self.shape, dtype=self.torch.float32, device="cuda")
+        snowlb3d_read(self.ctx, FIELDS3[field], out.data_ptr(), out.numel(), self.stream)
+        return out
+
+    def read_populations(self, name: str):
+        pset, q = POPS3[name]
+        out = self.torch.empty((q,) + self.shape, dtype=self.torch.float32, device="cuda")
+        snowlb3d_read_populations(self.ctx, pset, out.data_ptr(), out.numel(), self.stream)
+        return out if q > 1 else out[0]
+
+    def write_populations(self, name: str, values):
+        pset, q = POPS3[name]
+        t = self.torch.as_tensor(values, dtype=self.torch.float32, device="cuda").reshape((q,) + self.shape).contiguous()
+        snowlb3d_write_populations(self.ctx, pset, t.data_ptr(), t.numel(), self.stream)
+        self.torch.cuda.current_stream().synchronize()
+        return self
+
+    def set_state(self, f=None, g=None, h=None, phip=None):
+        for name, v in (("phip", phip), ("f", f), ("g", g), ("h", h)):
+            if v is not None:
+                self.write_populations(name, v)
+        return self
+
+    def diag(self) -> dict:
+        st, v = snowlb3d_diag(self.ctx, self.stream)
+        d = dict(zip(DIAG3_KEYS, v))
+        d["status"] = st
+        return d

@@ -156,3 +156,43 @@ def random_state(nx: int, ny: int, seed: int, flow: bool = True, amp: float = 0.
                                    + amp * rng.standard_normal((9, ny, nx)))
         out["f"] = f
     return out
+
+
+def random_state3d(nx: int, ny: int, nz: int, seed: int, flow: bool = True, amp: float = 0.02,
+                   n_blobs: int = 3) -> dict:
+    """A seeded, smooth, arbitrary 3D population state [q, z, y, x] (float64) for one-step parity
+    tests of the 3D step: phase populations spread around a few smooth balls (values in [-1, 1]) with
+    random shares, the exterior exactly -1 without noise (no gradients at rounding level); vapour and
+    flow populations positive with small smooth and random parts (the flow near rest).  Any state is a
+    legal input of the step; nothing here evaluates the method."""
+    rng = np.random.default_rng(seed)
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    s = -np.ones((nz, ny, nx))
+    for _ in range(n_blobs):
+        c = rng.uniform(0, 1, 3) * (nx, ny, nz)
+        R = rng.uniform(1.5, max(2.5, min(nx, ny, nz) / 3))
+        r = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        s = np.maximum(s, np.tanh((R - r) / math.sqrt(2.0)))
+    bulk = s < -1.0 + 1e-3
+    s = np.where(bulk, -1.0, s)
+    share7 = rng.uniform(0.5, 1.5, size=7)
+    share7 /= share7.sum()
+    h = share7[:, None, None, None] * s[None] + np.where(bulk, 0.0, amp * 0.1 * rng.standard_normal((7,) + s.shape))
+    U = 0.3 + 0.2 * np.sin(2 * math.pi * x / nx) * np.cos(2 * math.pi * y / ny) * np.cos(2 * math.pi * z / nz)
+    share7g = rng.uniform(0.5, 1.5, size=7)
+    share7g /= share7g.sum()
+    g = share7g[:, None, None, None] * U[None] * (1 + amp * rng.standard_normal((7,) + s.shape))
+    phip = s + np.where(bulk, 0.0, amp * rng.standard_normal(s.shape))
+    out = {"g": g, "h": h, "phip": phip}
+    if flow:
+        base = np.array([12.0] + [2.0] * 6 + [1.0] * 12) / 36.0
+        out["f"] = base[:, None, None, None] * (1.0 + 0.05 * np.sin(2 * math.pi * (x + 2 * y + 3 * z) / nx)[None]
+                                                + amp * rng.standard_normal((19,) + s.shape))
+    return out
+
+
+# F4: the three-dimensional extension (Sec. 4 proposes it).  A ventilated crystal on 256 x 128 x 128
+# (4.2M cells, as many as the 2048^2 workload): inlet u = 0.01 at x = 0, outlet at x = 255, periodic y
+# and z, the 2048^2 workload's physics otherwise, spherical seed R = 8 at (80, 64, 64).
+F4_3D = dict(COMMON, name="f4_ventilated_3d_256x128x128", nx=256, ny=128, nz=128, flow=1, inout=1, u_in=0.01,
+             U_in=0.6, U0=0.6, seed=(80.0, 64.0, 64.0, 8.0), w_init=1.0, steps=2000)

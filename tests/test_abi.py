@@ -12,9 +12,14 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "snowlb.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(snowlb_[a-z_0-9]+)\s*\(", txt)))
+    """Every function declared in include/*.h (comments stripped)."""
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(snowlb(?:3d)?_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_header_symbols_exported_and_bound():
@@ -145,3 +150,25 @@ def test_diagnostics_count_matches_header():
     m = re.search(r"#define\s+SNOWLB_DIAG_COUNT\s+(\d+)", txt)
     assert m and int(m.group(1)) == S.DIAG_COUNT == len(S.DIAG_KEYS) == 9
     assert S.DIAG_KEYS[8] == "species"
+
+
+def test_3d_parameters_validated_before_gpu():
+    """The 3D entry points validate like the 2D ones: defaults are valid, and out-of-range values are
+    rejected with a message before any GPU call (snowlb3d_create fails with EINVAL and a NULL ctx)."""
+    assert "snowlb3d_step" in header_functions() and "snowlb3d_diag" in header_functions()
+    p = S.snowlb3d_params_default()
+    assert S.snowlb3d_validate(p) == (0, "")
+    assert (p.nx, p.ny, p.nz, p.flow) == (64, 64, 64, 0)
+    for field, value, frag in (("nz", 1, "nz"), ("tau_vap", 0.5, "tau_vap"), ("eps", 0.5, "eps"),
+                               ("bc_x", 1, "inflow/outflow"), ("init_width", 0.0, "init_width"),
+                               ("nx", 4096, "too large")):
+        q = S.snowlb3d_params_default()
+        setattr(q, field, value)
+        if field == "nx":
+            q.ny, q.nz, q.flow = 4096, 64, 1
+        st, msg = S.snowlb3d_validate(q)
+        assert st == S.EINVAL and frag in msg, (field, msg)
+        ctx = ctypes.c_void_p(123)
+        assert S.lib().snowlb3d_create(ctypes.byref(q), ctypes.byref(ctx)) == S.EINVAL and not ctx.value
+        assert frag in S.lib().snowlb3d_last_error(None).decode()
+    assert S.lib().snowlb3d_step(None, 1, None) == S.EINVAL and S.lib().snowlb3d_step_count(None) == -1
