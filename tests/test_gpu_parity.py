@@ -385,10 +385,31 @@ def round_fmt(x, storage):
     return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
+def fma32(a, b, c):
+    """float32 fused multiply-add, fl32(a b + c) with one rounding, emulated exactly: a and b are
+    float32 values of at most 24 significant bits, so a b is exact in float64; s = fl64(a b + c) with
+    the error-free remainder e; rounding s to float32 is then the correct rounding of a b + c unless s
+    is exactly halfway between two float32 values and e != 0 (asserted not to happen)."""
+    a64, b64, c64 = (np.asarray(v, np.float32).astype(np.float64) for v in (a, b, c))
+    p = a64 * b64
+    s = p + c64
+    bp = s - p
+    e = (p - (s - bp)) + (c64 - bp)
+    r = s.astype(np.float32)
+    r64 = r.astype(np.float64)
+    up = np.nextafter(r, np.float32(np.inf)).astype(np.float64)
+    dn = np.nextafter(r, np.float32(-np.inf)).astype(np.float64)
+    tie = (e != 0) & ((2 * s == r64 + up) | (2 * s == r64 + dn))
+    assert not tie.any()
+    return r.astype(np.float64)
+
+
 def decode32(w, m, d):
-    """p = w (m + d) in FP32 arithmetic, as the library decodes."""
+    """The library's decode of a 16-bit deviation d against the reference m: p = fma(w, d, fl32(w m))
+    in FP32 (one product rounded, then one fused multiply-add)."""
     f = np.float32
-    return (np.asarray(w, f) * (np.asarray(m, f) + np.asarray(d, f))).astype(f).astype(np.float64)
+    wm = (np.asarray(w, f).astype(np.float64) * np.asarray(m, f).astype(np.float64)).astype(f)
+    return fma32(w, d, wm)
 
 
 def ghost_refs(storage, cfg):
@@ -481,8 +502,8 @@ def test_half_storage_one_step(case, storage, stencil):
     sim = S.Sim(cfg, storage=storage)
     sim.set_state(**{k: torch.from_numpy(v) for k, v in qs.items()})
     back = gpu_state(sim, cfg["flow"])
-    for k in back:  # the library holds exactly the quantized values (to FP32 rounding)
-        assert np.abs(back[k] - qs[k]).max() <= 1e-6 * max(1.0, np.abs(qs[k]).max()), k
+    for k in back:  # the library holds exactly the quantized values: both sides start bitwise equal
+        assert np.array_equal(back[k], qs[k]), (k, np.abs(back[k] - qs[k]).max())
     refs = source_refs(qs, cfg)
     o.step(1)
     sim.step(1)
@@ -570,16 +591,22 @@ def test_c2_1024_full_length_crop_against_oracle():
     assert errs["phi"] <= C2_20K_PHI_BAR
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+BF16_2048_MISS = pytest.mark.xfail(
+    strict=False,
+    reason="BF16 storage misses the 1e-2 phase-field target after 10^4 ventilated steps at 2048^2 "
+           "(1.4e-2 to 1.9e-2 measured on the moving interface, mean 1.3e-6): its 8-bit mantissa puts "
+           "rounding noise into every population at a level the run's own sensitivity amplifies to that "
+           "size; referencing h to its source cell's phi (1.44e-2) or g to the post-source vapour (1.85e-2) "
+           "did not close it.  FP16 meets the target.")
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", pytest.param("bf16", marks=BF16_2048_MISS)])
 def test_c3_2048_crop_against_oracle(storage):
     """The half-storage workload at its own size against the FP64 oracle: the 2048^2 ventilated
     lattice over its 10^4 steps in each storage format, compared on the 512^2 crop around the crystal
     (rows 768..1279, columns 44..555) with the oracle's fields after the same run, stored (rounded to
-    float32) by tests/golden/make_oracle_crop.py.  Measured phase-field errors: FP32 2.4e-4, FP16 7.4e-3,
-    BF16 1.5e-2.  FP32 is held to 1e-3 as in the 512^2 run (over 10^4 ventilated steps its error
-    passes 1e-4), FP16 to the 1e-2 half-storage target.  BF16 misses that target at this size (its
-    8-bit mantissa, on deviations that are largest on the moving interface, where the maximum sits);
-    it is held to 2e-2 so that a regression still fails."""
+    float32) by tests/golden/make_oracle_crop.py.  FP32 is held to 1e-3 as in the 512^2 run (over 10^4
+    ventilated steps its error passes 1e-4); FP16 and BF16 to the 1e-2 half-storage target."""
     data = np.load(GOLDEN_C3)
     cfg = W.C3
     (r0, r1), (c0, c1) = cfg["crop"]
@@ -593,7 +620,7 @@ def test_c3_2048_crop_against_oracle(storage):
         report("2048^2 crop 10k %s %s" % (storage, k), errs[k])
     del sim
     torch.cuda.empty_cache()
-    assert errs["phi"] <= {"fp32": 1e-3, "fp16": 1e-2, "bf16": 2e-2}[storage]
+    assert errs["phi"] <= {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2}[storage]
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
@@ -608,7 +635,7 @@ def test_write_field_sets_a_consistent_state(storage):
     phi = np.tanh((8.0 - np.hypot(xx - 50.3, yy - 39.6)) / np.sqrt(2.0)).astype(np.float32)
     U = (0.4 + 0.1 * np.sin(2 * np.pi * xx / 96) * np.cos(2 * np.pi * yy / 80)).astype(np.float32)
     sim.write_field("phi", phi).write_field("U", U)
-    tol = {"fp32": 1e-6, "fp16": 2e-3, "bf16": 2e-2}[storage]
+    tol = {"fp32": 1e-6, "fp16": 2e-3, "bf16": 1e-2}[storage]
     e_phi = float(np.abs(sim.read("phi").cpu().numpy() - phi).max())
     e_U = float(np.abs(sim.read("U").cpu().numpy() - U).max())
     report("write_field %s phi" % storage, e_phi)
@@ -621,7 +648,7 @@ def test_write_field_sets_a_consistent_state(storage):
     F = o.fields()
     err = max(float(np.abs(sim.read(k).double().cpu().numpy() - F[k]).max()) for k in ("phi", "U", "rho"))
     report("write_field %s then 20 steps" % storage, err)
-    assert err < {"fp32": 1e-5, "fp16": 5e-3, "bf16": 5e-2}[storage]
+    assert err < {"fp32": 1e-5, "fp16": 5e-4, "bf16": 5e-3}[storage]
     with pytest.raises(S.SnowlbError):
         sim.write_field("rho", phi)
 
@@ -662,13 +689,13 @@ def _ventilated_512_oracle(cfg):
     return _ORACLE_CACHE[key]
 
 
-def test_half_storage_2048_against_fp32_storage():
+@pytest.mark.parametrize("storage", ["fp16", pytest.param("bf16", marks=BF16_2048_MISS)])
+def test_half_storage_2048_against_fp32_storage(storage):
     """The half-storage workload at its own size: the 2048^2 ventilated lattice over its 10^4 steps in
-    FP16 and BF16 storage against the same run in FP32 storage (the oracle comparison of these formats
+    FP16 or BF16 storage against the same run in FP32 storage (the oracle comparison of these formats
     is the 512^2 run above).  Max and mean absolute differences are printed per field.  The phase
     field's largest difference sits on the moving interface, where a shift of the front by a fraction
-    of a cell shows up in full: FP16 is held to 1e-2 (7.2e-3 measured), BF16 to 2e-2 (1.5e-2
-    measured, mean 1.3e-6; against the oracle at 512^2 it is within 1e-2)."""
+    of a cell shows up in full; it is held to the 1e-2 half-storage target."""
     cfg = W.C3
     fields = ("phi", "U", "rho", "ux", "uy")
     ref = {}
@@ -676,13 +703,14 @@ def test_half_storage_2048_against_fp32_storage():
     for k in fields:
         ref[k] = sim.read(k).double()
     del sim
-    for storage in ("fp16", "bf16"):
-        sim = S.Sim(cfg, storage=storage).init().step(cfg["steps"])
-        for k in fields:
-            d = (sim.read(k).double() - ref[k]).abs()
-            mx, mean = float(d.max()), float(d.mean())
-            print("  2048^2 10k %s vs fp32 %-4s max %.3e mean %.3e" % (storage, k, mx, mean), flush=True)
-            if k == "phi":
-                assert mx <= (1e-2 if storage == "fp16" else 2e-2), (storage, mx)
-        del sim
+    sim = S.Sim(cfg, storage=storage).init().step(cfg["steps"])
+    worst = 0.0
+    for k in fields:
+        d = (sim.read(k).double() - ref[k]).abs()
+        mx, mean = float(d.max()), float(d.mean())
+        print("  2048^2 10k %s vs fp32 %-4s max %.3e mean %.3e" % (storage, k, mx, mean), flush=True)
+        if k == "phi":
+            worst = mx
+    del sim
     torch.cuda.empty_cache()
+    assert worst <= 1e-2, (storage, worst)
