@@ -40,7 +40,7 @@ extern "C" {
 
 typedef struct {
     int32_t nx, ny, nz;  /* lattice size, 2 <= each <= 65535; the populations of one copy padded
-                            to whole 16 x 4 x 4 blocks within 4 GiB (about 32M cells with flow)      */
+                            to whole 64 x 2 x 2 blocks within 4 GiB (about 32M cells with flow)      */
     int32_t flow;        /* 1: D3Q19 flow on; 0: u = 0                                                */
     int32_t bc_x;        /* SNOWLB_BC_PERIODIC or SNOWLB_BC_INOUT (needs flow = 1)                    */
     int32_t diag_every;  /* > 0: snowlb3d_step checks for non-finite values every this many steps     */

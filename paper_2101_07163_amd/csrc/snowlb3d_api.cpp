@@ -1,6 +1,6 @@
 // snowlb3d_api.cpp -- host runtime and C ABI of the 3D step (see include/snowlb3d.h): parameter
 // validation before any HIP call, one allocation per lattice (two population copies and two phi_prev
-// planes in 16 x 4 x 4 blocks), graph-replayed step loops, field read-out, population exchange and
+// planes in blocks of cells), graph-replayed step loops, field read-out, population exchange and
 // FP64 diagnostics.
 #include <hip/hip_runtime.h>
 
@@ -33,7 +33,7 @@ const char* validate3(const snowlb3d_params* p) {
     if (p->nx > 65535 || p->ny > 65535 || p->nz > 65535) return "lattice too large (nx, ny, nz <= 65535)";
     const int64_t cells = round_up(p->nx, kBX) * round_up(p->ny, kBY) * round_up(p->nz, kBZ);
     if (cells * (p->flow ? 33 : 14) * 4 > (int64_t(1) << 32))
-        return "lattice too large (the populations of one copy, padded to 16 x 4 x 4 blocks, within 4 GiB)";
+        return "lattice too large (the populations of one copy, padded to whole blocks, within 4 GiB)";
     if (p->flow != 0 && p->flow != 1) return "flow must be 0 or 1";
     if (p->bc_x != SNOWLB_BC_PERIODIC && p->bc_x != SNOWLB_BC_INOUT) return "unknown bc_x";
     if (p->bc_x == SNOWLB_BC_INOUT && !p->flow) return "inflow/outflow needs flow = 1";

@@ -5,7 +5,7 @@
 // z (c) axis, a = 1 + eps Re((n_x + i n_y)^6), which is the paper's 1 + eps cos 6 theta for normals in
 // the basal plane; x periodic or inlet/outlet, y and z periodic.
 //
-// k_step3 is one fused step per 16 x 4 x 4 block of cells, built like the 2D k_step: the block's h
+// k_step3 is one fused step per block of 64 x 2 x 2 cells, built like the 2D k_step: the block's h
 // and phi (FP64) are staged with a one-cell halo in LDS (the gradient and the destination term
 // h_q(x + c_q, t) of Eq. (d)), each cell collides all three populations and pushes them to their
 // destinations, and every (destination, q) is written by exactly one thread.  FP32 storage; the
@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
     const Dom3& d = *dp;
 
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = (tid >> 4) & 3, tz = tid >> 6;
+    const int tx = tid & (kBX - 1), ty = (tid >> kSX) & (kBY - 1), tz = tid >> (kSX + kSY);
     // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid)
     const int G = gridDim.x, b = blockIdx.x;
     const int t = xcd_remap ? (b % 8) * (G / 8) + min(b % 8, G % 8) + b / 8 : b;

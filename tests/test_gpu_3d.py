@@ -43,7 +43,7 @@ def report(name, err):
 @pytest.mark.parametrize("case", list(CASES))
 @pytest.mark.parametrize("shape", [(20, 9, 7), (33, 12, 10), (2, 2, 2), (3, 5, 2)])
 def test_one_step_from_random_state_3d(case, shape):
-    """One step from the same arbitrary FP32 state on both sides, ragged against the 16 x 4 x 4 blocks
+    """One step from the same arbitrary FP32 state on both sides, ragged against the 64 x 2 x 2 blocks
     (and lattices smaller than one block, where the halo wraps onto the block): every population within
     2e-6 of the FP64 oracle."""
     nx, ny, nz = shape
