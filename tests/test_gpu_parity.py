@@ -5,6 +5,7 @@ population; the 128^2 plain workload keeps the phase field within 1e-4 of the or
 steps; full-size workloads agree after a few steps on every field.  Integer-like outputs (the
 solid-cell count) are compared exactly where the oracle's decision and the GPU's agree in precision.
 """
+import json
 import os
 
 import numpy as np
@@ -540,9 +541,9 @@ def test_half_storage_c1_plain_128(storage):
 def test_ventilated_512_long_run(storage):
     """The 2048^2 half-storage workload's physics (inlet u = 0.01, U_in = U0 = 0.6, seed R = 8) on a
     512^2 lattice with the seed at (150, 256), 10000 steps, against the FP64 oracle.  Errors per
-    field are printed; the phase field bar is 1e-2 for FP16 and BF16 storage.  FP32 storage is bounded at
-    1e-3: over 10^4 ventilated steps its error grows past 1e-4 (5e-4 measured), through the pressure
-    level that the open inlet/outlet pair lets FP32 rounding move."""
+    field are printed; the phase field bar is 1e-2 for FP16 and BF16 storage.  FP32 storage is held to
+    the derived bar max(1e-4, 2 x the oracle's own spread under one-ulp noise per step), with 1e-3 as a
+    hard regression guard."""
     cfg = dict(W.C3)
     cfg.update(nx=512, ny=512, seed=(150.0, 256.0, 8.0))
     o = _ventilated_512_oracle(cfg)
@@ -552,31 +553,45 @@ def test_ventilated_512_long_run(storage):
     for k, v in errs.items():
         report("512^2 10k %s %s" % (storage, k), v)
     if storage == "fp32":
-        assert errs["phi"] <= 1e-3
+        assert errs["phi"] <= 1e-3  # regression guard
+        bar = derived_bar("v512", 10000)
+        assert bar is not None
+        print("  512^2 10k fp32 phi %.3e against the derived bar %.3e" % (errs["phi"], bar), flush=True)
+        if errs["phi"] > bar:
+            pytest.xfail("FP32 phase field %.2e after 10^4 steps at 512^2 exceeds twice the FP64 oracle's own "
+                         "spread under one-ulp noise per step (bar %.2e): the FP32 run carries an error "
+                         "component beyond that sensitivity, not found" % (errs["phi"], bar))
     else:
         assert errs["phi"] <= 1e-2
 
 
 GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_crop_10000.npz")
+SPREAD_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_spread.json")
+
+
+def derived_bar(case, step):
+    """Phase-field bar of a long ventilated FP32 run: the 1e-4 target, or twice how far the FP64
+    oracle's own phase field moves under noise of one FP32 ulp per value and step where that is larger
+    (the spread stored by tests/golden/make_oracle_spread.py); None if the spread is not stored."""
+    if not os.path.exists(SPREAD_JSON):
+        return None
+    d = json.load(open(SPREAD_JSON)).get(case)
+    if not d or str(step) not in d["spread_phi"]:
+        return None
+    return max(1e-4, 2.0 * d["spread_phi"][str(step)])
 
 
 GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c2_crop_20000.npz")
-
-
-# The phase-field bar of the full-length 1024^2 run: the FP32 run differs from the oracle by 2.0e-3
-# after 2*10^4 steps.  The 1e-4 target holds to 5000 steps (the checkpoint test above); beyond that the
-# run's own sensitivity to rounding-sized perturbations grows past it (see the docstring below).
-C2_20K_PHI_BAR = 4e-3
 
 
 def test_c2_1024_full_length_crop_against_oracle():
     """The 1024^2 ventilated workload over its full 2*10^4 steps in FP32 storage against the FP64
     oracle's fields after the same run, on the 512^2 crop around the crystal (rows 256..767, columns
     44..555), stored by tests/golden/make_oracle_crop.py.  Measured: phase field 2.0e-3, U 2.6e-4,
-    rho 1.3e-5, u 7.7e-6.  The phase-field target of 1e-4 is missed at this length: relative noise of
-    9.5e-7 every 100 steps applied to the FP64 oracle's own state (about three times the random walk
-    of FP32 rounding) moves its phase field by 1.3e-4 after 10^4 steps and 5.5e-3 after 2*10^4, more than
-    the FP32 run's difference: at this length the run's own sensitivity, not the kernel, sets the error."""
+    rho 1.3e-5, u 7.7e-6.  The bar is derived: max(1e-4, 2 x the FP64 oracle's own spread at 2*10^4
+    steps under one-ulp noise per value and step), stored by tests/golden/make_oracle_spread.py (the
+    spread is 2.2e-3 there, 1.9e-4 at 10^4 steps): at this length the run's own sensitivity, not the
+    kernel, sets the error."""
     data = np.load(GOLDEN_C2)
     cfg = W.C2
     (r0, r1), (c0, c1) = [tuple(int(v) for v in data["rows"]), tuple(int(v) for v in data["cols"])]
@@ -588,7 +603,10 @@ def test_c2_1024_full_length_crop_against_oracle():
         errs[k] = float(np.abs(got - data[k].astype(np.float64)).max())
         report("1024^2 crop 20k fp32 %s" % k, errs[k])
     del sim
-    assert errs["phi"] <= C2_20K_PHI_BAR
+    bar = derived_bar("c2", 20000)
+    assert bar is not None
+    print("  1024^2 crop 20k fp32 phi %.3e against the derived bar %.3e" % (errs["phi"], bar), flush=True)
+    assert errs["phi"] <= bar
 
 
 BF16_2048_MISS = pytest.mark.xfail(
@@ -605,8 +623,9 @@ def test_c3_2048_crop_against_oracle(storage):
     """The half-storage workload at its own size against the FP64 oracle: the 2048^2 ventilated
     lattice over its 10^4 steps in each storage format, compared on the 512^2 crop around the crystal
     (rows 768..1279, columns 44..555) with the oracle's fields after the same run, stored (rounded to
-    float32) by tests/golden/make_oracle_crop.py.  FP32 is held to 1e-3 as in the 512^2 run (over 10^4
-    ventilated steps its error passes 1e-4); FP16 and BF16 to the 1e-2 half-storage target."""
+    float32) by tests/golden/make_oracle_crop.py.  FP32 is held to the derived bar max(1e-4, 2 x the
+    oracle's own spread) where the spread of this run is stored, else to 1e-3; FP16 and BF16 to the
+    1e-2 half-storage target."""
     data = np.load(GOLDEN_C3)
     cfg = W.C3
     (r0, r1), (c0, c1) = cfg["crop"]
@@ -620,7 +639,11 @@ def test_c3_2048_crop_against_oracle(storage):
         report("2048^2 crop 10k %s %s" % (storage, k), errs[k])
     del sim
     torch.cuda.empty_cache()
-    assert errs["phi"] <= {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2}[storage]
+    bar = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2}[storage]
+    if storage == "fp32" and derived_bar("c3", 10000) is not None:
+        bar = derived_bar("c3", 10000)
+        print("  2048^2 crop 10k fp32 phi %.3e against the derived bar %.3e" % (errs["phi"], bar), flush=True)
+    assert errs["phi"] <= bar
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
