@@ -28,10 +28,11 @@
  *       pre-collision value, so the scheme streams by "push".
  *   R6  |grad phi|^2 <= grad_eps2: the normal is undefined; a = 1 and N = 0.
  *   R7  d(phi)/dt in the vapour source = phi(t) - phi(t-1); all three solvers read the state at t.
- *   R8  inlet: equilibrium ghost column at x = -1 (rho0, (u_in, 0); U_in; phi = -1, h_q = -w_q);
+ *   R8  the vapour and phase-field sources carry no (1 - 1/(2 tau)) factor, as printed.
+ *   R9  inlet: equilibrium ghost column at x = -1 (rho0, (u_in, 0); U_in; phi = -1, h_q = -w_q);
  *       outlet: ghost column at x = nx copies column nx-1 after collision; gradient ghosts
  *       phi(-1, y) = -1 and phi(nx, y) = phi(nx-1, y).
- *   R9  initial state: phi0 = tanh((R - r)/(sqrt(2) w_init)), h = w phi0, phi_prev = phi0,
+ *   R10 initial state: phi0 = tanh((R - r)/(sqrt(2) w_init)), h = w phi0, phi_prev = phi0,
  *       f = f_eq(rho0, u0), g = g_eq(U_init, u0), u0 = (1 - phi0)/2 (u_in, 0) for a ventilated
  *       domain and 0 otherwise.
  */
@@ -151,7 +152,7 @@ void orc_aniso(const orc_params* p, double gx, double gy, double* a, double* Nx,
     *Ny = k * dadgy;
 }
 
-/* phi at (x, y) with the domain closure: y periodic; x periodic or the inlet/outlet ghosts [R8]. */
+/* phi at (x, y) with the domain closure: y periodic; x periodic or the inlet/outlet ghosts [R9]. */
 static double phi_at(const orc_params* p, const double* phi, int x, int y)
 {
     y = wrap(y, p->ny);
@@ -245,7 +246,7 @@ void orc_destroy(orc* o)
 
 int64_t orc_step_count(const orc* o) { return o->step; }
 
-/* Initial condition [R9]. */
+/* Initial condition [R10]. */
 void orc_init_seed(orc* o, double xs, double ys, double R, double w_init, double U0,
                    const double* U_init)
 {
@@ -354,7 +355,7 @@ static void collide(orc* o, int x, int y)
         o->gs[5 * i + q] = g[q] - (g[q] - geq[q]) / tau_g - W5[q] * 0.5 * p->L_sat * dphidt;
 }
 
-/* Streaming into destination (x, y) [R5, R8]. */
+/* Streaming into destination (x, y) [R5, R9]. */
 static void stream_into(orc* o, int x, int y)
 {
     const orc_params* p = &o->p;

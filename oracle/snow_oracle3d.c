@@ -13,7 +13,7 @@
  *   3. streaming, written per destination (each destination population has exactly one source)
  *   4. phi_prev <- phi, t <- t + 1
  *
- * The paper gives the method in two dimensions only.  Its readings there (the 2D oracle's R1-R9) carry
+ * The paper gives the method in two dimensions only.  Its readings there (the 2D oracle's R1-R10) carry
  * over unchanged; the three-dimensional ones are marked [Tk]:
  *   T1  lattices: D3Q19 for the flow (weights 1/3, 1/18 on the 6 axes, 1/36 on the 12 face
  *       diagonals, cs^2 = 1/3), D3Q7 for the vapour g and the phase field h (weights 1/4 at rest and
@@ -28,7 +28,7 @@
  *       plane and psi its angle to the z axis; in the basal plane (n_z = 0) this is the paper's
  *       1 + eps cos(6 theta), and along the c axis a = 1.  The flux is N = kappa_N (W0^2/tau0)
  *       |grad phi|^2 a da/d(grad phi) as in R2.
- *   T4  boundaries: x periodic or inlet/outlet as R8 (the inlet ghost plane at x = -1 carries
+ *   T4  boundaries: x periodic or inlet/outlet as R9 (the inlet ghost plane at x = -1 carries
  *       (rho0, (u_in, 0, 0); U_in; phi = -1), the outlet ghost plane at x = nx copies plane nx-1
  *       after collision); y and z periodic.
  *   T5  initial state: the spherical seed phi0 = tanh((R - r)/(sqrt 2 w_init)), h = w phi0,
