@@ -18,13 +18,14 @@ Cases (regions are the cells the GPU tests compare):
   c4    each of the 64 crystals over 5000 steps, the box around its crystal (phi > -0.9, widened by
         16 cells); also stores each crystal's phi and U on that box (float32) in c4_members_5000.npz
 
-Results go to oracle_spread.json (merged with what is there).  It calls only the oracle; c4 and c3
-take about an hour each on 8 cores.
+Results go to oracle_spread.json (merged with what is there).  It calls only the oracle; c3 takes
+about an hour and c4 about four on 8 cores (c4 resumes after the last member stored).
 """
 import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -51,14 +52,43 @@ def new(cfg):
     return oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
 
 
-def perturb(o, rng, k):
+class Draws:
+    """The standard normal arrays of successive perturbations (f, g, h, phi_prev in that order, f only
+    with flow), drawn from one seeded generator in a worker thread while the oracle steps; the sequence
+    is the one a plain loop over the same generator gives."""
+
+    def __init__(self, o, rng):
+        names = ("f", "g", "h", "phip") if o.p.flow else ("g", "h", "phip")
+        ny, nx = o.shape
+        q = {"f": 9, "g": 5, "h": 9, "phip": 0}
+        self.shapes = [(n, (q[n], ny, nx) if q[n] else (ny, nx)) for n in names]
+        self.rng = rng
+        self.pool = ThreadPoolExecutor(max_workers=1)
+        self.next = self.pool.submit(self._draw)
+
+    def _draw(self):
+        return {n: self.rng.standard_normal(shape) for n, shape in self.shapes}
+
+    def take(self):
+        z = self.next.result()
+        self.next = self.pool.submit(self._draw)
+        return z
+
+    def close(self):
+        self.next.result()
+        self.pool.shutdown()
+
+
+def perturb(o, draws, k):
     s = o.get_state()
     a = SIGMA * np.sqrt(k)
-    for name in ("f", "g", "h", "phip"):
-        if name == "f" and not o.p.flow:
-            s[name] = None
-            continue
-        s[name] = s[name] * (1.0 + a * rng.standard_normal(s[name].shape))
+    z = draws.take()
+    if not o.p.flow:
+        s["f"] = None
+    for name, zn in z.items():
+        zn *= a
+        zn += 1.0
+        s[name] *= zn
     o.set_state(**s)
 
 
@@ -66,8 +96,8 @@ def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
     """phi spread at each checkpoint over region ((r0, r1), (c0, c1)); the reference runs alongside
     unless its phi on the region at the last checkpoint is given (ref_at_end)."""
     (r0, r1), (c0, c1) = region
-    rng = np.random.default_rng(seed)
     noisy = new(cfg)
+    draws = Draws(noisy, np.random.default_rng(seed))
     ref = None if ref_at_end is not None else new(cfg)
     out = {}
     done, t0 = 0, time.time()
@@ -77,12 +107,13 @@ def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
         if ref is not None:
             ref.step(k)
         done += k
-        perturb(noisy, rng, k)
+        perturb(noisy, draws, k)
         if done in checkpoints:
             a = noisy.fields()["phi"][r0:r1, c0:c1]
             b = ref.fields()["phi"][r0:r1, c0:c1] if ref is not None else ref_at_end
             out[str(done)] = float(np.abs(a - b).max())
             print("%s step %d spread %.3e (%.0f s)" % (log, done, out[str(done)], time.time() - t0), flush=True)
+    draws.close()
     return out
 
 
