@@ -117,6 +117,7 @@ void fill_dom3(snowlb3d_ctx* c) {
     d.tauv_m_half = (float)(p.tau_vap - 0.5);
     d.omega_f = (float)(1.0 / p.tau_f);
     d.guo = (float)(1.0 - 0.5 / p.tau_f);
+    d.tauf_m_half = (float)(p.tau_f - 0.5);
     d.kdrag = (float)(p.h_drag * nu / (4.0 * p.W0 * p.W0));
     d.rho0 = (float)p.rho0;
     d.u_in = (float)p.u_in;

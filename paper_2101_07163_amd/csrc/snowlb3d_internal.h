@@ -37,9 +37,9 @@ struct Dom3 {
     float* phip[2];  // phi(t-1), one plane each
     double grad_eps2;
     float eps, Dphi, coefN, inv_tau0, lam, half_Lsat, tauv_m_half, omega_f, guo, kdrag, rho0, u_in, U_in;
+    float tauf_m_half;  // tau_f - 1/2 (= guo / omega_f)
     float df_in[19];  // inlet ghost f_eq(rho0, (u_in, 0, 0)) - w
     float g_in[7];    // inlet ghost g_eq(U_in, (u_in, 0, 0))
-    float pad1;
 };
 
 // One step of every block of the lattice, reading copy par and writing copy 1 - par.

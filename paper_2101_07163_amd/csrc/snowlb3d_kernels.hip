@@ -189,21 +189,30 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
         uy = (float)jy64 * sc;
         uz = (float)jz64 * sc;
         const float Fx = -k * ux, Fy = -k * uy, Fz = -k * uz;
-        const float uu = ux * ux + uy * uy + uz * uz, uF = ux * Fx + uy * Fy + uz * Fz;
-        float s8 = 0.f, sS = 0.f, feq[19], Sg[19];
-#pragma unroll
-        for (int q = 1; q < 19; ++q) {
-            const float cu = CX[q] * ux + CY[q] * uy + CZ[q] * uz;
-            const float cF = CX[q] * Fx + CY[q] * Fy + CZ[q] * Fz;
-            feq[q] = W19[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-            Sg[q] = d.guo * W19[q] * (3.f * (cF - uF) + 9.f * cu * cF);
-            s8 += feq[q];
-            sS += Sg[q];
-        }
-        feq[0] = drho - s8;
-        Sg[0] = -sS;
-#pragma unroll
-        for (int q = 0; q < 19; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
+        const float uu = ux * ux + uy * uy + uz * uz;
+        // BGK relaxation with the Guo term of F = -k u, as relaxation toward a shifted target:
+        // fs_q = f_q - omega (f_q - T_q), T_q = f_eq,q - w_q + S_q / omega (exact in real arithmetic;
+        // f_q - T_q is small near equilibrium) = w_q (A + Bc c.u + Cc (c.u)^2) with G = (tau_f - 1/2) k,
+        // A = drho - (1.5 rho - 3 G) u.u, Bc = 3 (rho - G), Cc = 4.5 rho - 9 G; opposite velocities
+        // share w (A + Cc (c.u)^2).  fs_0 and the axis populations fs_1, fs_3, fs_5 are replaced by
+        // the closure below.
+        const float omf = d.omega_f, G = d.tauf_m_half * k;
+        const float A = drho - (1.5f * rho - 3.f * G) * uu;
+        const float Bc = 3.f * (rho - G), Cc = 4.5f * rho - 9.f * G;
+        auto pair = [&](int q, int qb, float cu) {  // q along c, qb along -c
+            const float S0 = W19[q] * __builtin_fmaf(Cc * cu, cu, A), D = W19[q] * Bc * cu;
+            fs[q] = __builtin_fmaf(-omf, f[q] - (S0 + D), f[q]);
+            fs[qb] = __builtin_fmaf(-omf, f[qb] - (S0 - D), f[qb]);
+        };
+        pair(1, 2, ux);
+        pair(3, 4, uy);
+        pair(5, 6, uz);
+        pair(7, 8, ux + uy);
+        pair(9, 10, ux - uy);
+        pair(11, 12, ux + uz);
+        pair(13, 14, ux - uz);
+        pair(15, 16, uy + uz);
+        pair(17, 18, uy - uz);
         // after collision the first moments are j - omega (j - rho u) + (1 - omega/2) F and the zeroth
         // is unchanged: fs_1, fs_3, fs_5 (+x, +y, +z) take the first moments as remainders, fs_0 the
         // zeroth, every sum in FP64
@@ -241,38 +250,37 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
     const float srcg = d.half_Lsat * (phi - phip);
     float gs[7];
     {
-        float geq[7], sg6 = 0.f;
-#pragma unroll
-        for (int q = 1; q < 7; ++q) {
-            geq[q] = W7[q] * U * (1.f + 4.f * (CX[q] * ux + CY[q] * uy + CZ[q] * uz));
-            sg6 += geq[q];
-        }
-        geq[0] = U - sg6;
-#pragma unroll
-        for (int q = 1; q < 7; ++q) gs[q] = g[q] - (g[q] - geq[q]) * itg - W7[q] * srcg;
+        // relaxation toward g_eq = w U (1 + 4 c.u) and the source share w srcg, gathered:
+        // gs_q = (1 - itg) g_q + w (itg U - srcg) + 4 w itg U c.u (4 w = 1/2); gs_0 by the closure
+        const float G0 = W7[1] * (itg * U - srcg), G1 = 0.5f * itg * U, itc = 1.f - itg;
+        const float Gx = G1 * ux, Gy = G1 * uy, Gz = G1 * uz;
+        gs[1] = __builtin_fmaf(itc, g[1], G0 + Gx);
+        gs[2] = __builtin_fmaf(itc, g[2], G0 - Gx);
+        gs[3] = __builtin_fmaf(itc, g[3], G0 + Gy);
+        gs[4] = __builtin_fmaf(itc, g[4], G0 - Gy);
+        gs[5] = __builtin_fmaf(itc, g[5], G0 + Gz);
+        gs[6] = __builtin_fmaf(itc, g[6], G0 - Gz);
         double r64 = 0.0;
 #pragma unroll
         for (int q = 1; q < 7; ++q) r64 += (double)gs[q];
         gs[0] = (float)((U64 - (double)srcg) - r64);  // the zeroth moment after collision is U - src
     }
 
-    // phase field (Eq. (d)/(e) on D3Q7): equilibrium w (phi - c.N/cs^2), source w Q/tau0, rest as
-    // remainder
+    // phase field (Eq. (d)/(e) on D3Q7): relaxation toward w (phi - c.N/cs^2) plus the source share
+    // w Q/tau0, divided by a^2, gathered into P_q = ia2 (1 - ieta) h_q + ia2 (w K - 4 ieta w c.N) with
+    // K = ieta phi + srcQ; the rest population takes the remainder of the moving ones
     float P7[7];
     {
-        float heq[7], sh = 0.f, sQ = 0.f;
-#pragma unroll
-        for (int q = 1; q < 7; ++q) {
-            heq[q] = W7[q] * (phi - 4.f * (CX[q] * Nx + CY[q] * Ny + CZ[q] * Nz));
-            sh += heq[q];
-            sQ += W7[q] * srcQ;
-        }
-        heq[0] = phi - sh;
-#pragma unroll
-        for (int q = 0; q < 7; ++q) {
-            const float shq = q == 0 ? srcQ - sQ : W7[q] * srcQ;
-            P7[q] = (h[q] - (h[q] - heq[q]) * ieta + shq) * ia2;
-        }
+        const float hc = ia2 * (1.f - ieta), Ka = ia2 * __builtin_fmaf(ieta, phi, srcQ), Na = 4.f * ia2 * ieta;
+        const float S0 = W7[1] * Ka, Dx = W7[1] * Na * Nx, Dy = W7[1] * Na * Ny, Dz = W7[1] * Na * Nz;
+        const float H1 = S0 - Dx, H2 = S0 + Dx, H3 = S0 - Dy, H4 = S0 + Dy, H5 = S0 - Dz, H6 = S0 + Dz;
+        P7[1] = __builtin_fmaf(hc, h[1], H1);
+        P7[2] = __builtin_fmaf(hc, h[2], H2);
+        P7[3] = __builtin_fmaf(hc, h[3], H3);
+        P7[4] = __builtin_fmaf(hc, h[4], H4);
+        P7[5] = __builtin_fmaf(hc, h[5], H5);
+        P7[6] = __builtin_fmaf(hc, h[6], H6);
+        P7[0] = __builtin_fmaf(hc, h[0], Ka - (((H1 + H2) + (H3 + H4)) + (H5 + H6)));
     }
 
     // push streaming into copy 1 - par; destinations with the closure
@@ -518,22 +526,31 @@ __global__ void __launch_bounds__(kDiagThreads) k_diag3(Dom3 d, int par, double*
     }
 }
 
-__global__ void k_diag3_final(const double* partials, int nblk, double half_Lsat, double* out) {
-    if (threadIdx.x != 0) return;
-    double t[kDiagQ];
-    for (int k = 0; k < kDiagQ; ++k) {
-        double v = 0.0;
-        for (int b = 0; b < nblk; ++b) v += partials[(int64_t)b * kDiagQ + k];
-        t[k] = v;
-        out[k] = v;
+__global__ void __launch_bounds__(kDiagQ * 32) k_diag3_final(const double* __restrict__ partials, int nblk,
+                                                             double half_Lsat, double* __restrict__ out) {
+    // 32 lanes per quantity: lane l of quantity k sums blocks l, l + 32, ... in order, then lane 0 adds
+    // the 32 lane sums in order (fixed order, hence deterministic); then the species invariant.
+    __shared__ double s[kDiagQ][32];
+    __shared__ double tot[kDiagQ];
+    const int k = threadIdx.x / 32, l = threadIdx.x % 32;
+    double v = 0.0;
+    for (int b = l; b < nblk; b += 32) v += partials[(int64_t)b * kDiagQ + k];
+    s[k][l] = v;
+    __syncthreads();
+    if (l == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 32; ++i) t += s[k][i];
+        out[k] = t;
+        tot[k] = t;
     }
-    out[kDiagQ] = __dadd_rn(t[4], __dmul_rn(half_Lsat, t[6]));  // species invariant
+    __syncthreads();
+    if (threadIdx.x == 0) out[kDiagQ] = __dadd_rn(tot[4], __dmul_rn(half_Lsat, tot[6]));  // species invariant
 }
 
 hipError_t launch_diag3(const Dom3& d, int par, double* partials, double* out, double half_Lsat, hipStream_t s) {
     const int nb = diag_blocks3(d);
     hipLaunchKernelGGL(k_diag3, dim3(nb), dim3(kDiagThreads), 0, s, d, par, partials);
-    hipLaunchKernelGGL(k_diag3_final, dim3(1), dim3(64), 0, s, partials, nb, half_Lsat, out);
+    hipLaunchKernelGGL(k_diag3_final, dim3(1), dim3(kDiagQ * 32), 0, s, partials, nb, half_Lsat, out);
     return hipGetLastError();
 }
 

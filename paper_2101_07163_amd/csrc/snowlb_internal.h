@@ -84,7 +84,7 @@ struct DomDesc {
     int32_t sym;        // 1: vapour diffusivity switch q = 1 in both phases (thermal variant);
                         // 0: q = (1 - phi)/2 clamped to [0, 1]
     int32_t stencil;    // isotropic gradient: 2, 4 (one-cell reach) or 6, 8 (two-cell reach)
-    float pad_;
+    float tauf_m_half;  // tau_f - 1/2 (= guo / omega_f)
     double gw[5];       // gradient weights of the layers |c|^2 = 1, 2, 4, 5, 8 (Sec. 3.1.1, Table 1)
 };
 

@@ -60,8 +60,13 @@ __device__ __forceinline__ bool map_pos(const DomDesc& d, int gx, int gy, int& s
 // ---------------------------------------------------------------------------------------------
 // the fused step; RAD is the reach of the gradient stencil (1: E2, E4; 2: E6, E8), i.e. the width of
 // the halo ring staged in LDS
+// Occupancy floor: four waves per SIMD (at most 128 VGPRs) for the one-cell-reach tiles at least
+// four rows high, which fit without spilling; the others keep the compiler's own choice.
+template <int TY, int RAD>
+constexpr int kMinWaves = (RAD == 1 && TY >= 4) ? 4 : 1;
+
 template <int TX, int TY, class S, bool FLOW, bool INOUT, int RAD>
-__global__ void __launch_bounds__(TX * TY)
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(kMinWaves<TY, RAD>)))
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
@@ -378,26 +383,37 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                 uy = jy * sc;
                 const float Fx = -k * ux, Fy = -k * uy;
                 const float uu = ux * ux + uy * uy;
-                const float uF = ux * Fx + uy * Fy;
-                float feq[9], Sg[9];
+                // BGK relaxation with the Guo term of F = -k u, written as relaxation toward a shifted
+                // target: fs_q = f_q - omega (f_q - T_q) with T_q = f_eq,q - w_q + S_q / omega (exact in
+                // real arithmetic; the difference f_q - T_q is small near equilibrium, so the update keeps
+                // its accuracy in uniform streams).  T_q = w_q (A + Bc c.u + Cc (c.u)^2) with, for
+                // G = (tau_f - 1/2) k = guo k / omega,
+                //   A = drho - (1.5 rho - 3 G) u.u,  Bc = 3 (rho - G),  Cc = 4.5 rho - 9 G;
+                // opposite velocities share w (A + Cc (c.u)^2) and differ in the sign of w Bc c.u; the
+                // rest population takes the remainder of the moving ones
+                const float omf = d.omega_f, G = d.tauf_m_half * k;
+                const float A = drho - (1.5f * rho - 3.f * G) * uu;
+                const float Bc = 3.f * (rho - G), Cc = 4.5f * rho - 9.f * G;
+                float Tq[9];
+                auto pair = [&](int q, int qb, float cu) {  // q along c, qb along -c
+                    const float S0 = W9[q] * __builtin_fmaf(Cc * cu, cu, A), D = W9[q] * Bc * cu;
+                    Tq[q] = S0 + D;
+                    Tq[qb] = S0 - D;
+                };
+                pair(1, 3, ux);
+                pair(2, 4, uy);
+                pair(5, 7, ux + uy);
+                pair(6, 8, uy - ux);
+                Tq[0] = drho - sum8(Tq);
 #pragma unroll
-                for (int q = 1; q < 9; ++q) {
-                    const float cu = CX[q] * ux + CY[q] * uy;
-                    const float cF = CX[q] * Fx + CY[q] * Fy;
-                    feq[q] = W9[q] * (drho + rho * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
-                    Sg[q] = d.guo * W9[q] * (3.f * (cF - uF) + 9.f * cu * cF);
-                }
-                feq[0] = drho - sum8(feq);
-                Sg[0] = -sum8(Sg);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) fs[q] = f[q] - (f[q] - feq[q]) * d.omega_f + Sg[q];
+                for (int q = 0; q < 9; ++q) fs[q] = __builtin_fmaf(-omf, f[q] - Tq[q], f[q]);
                 if (EXACT) {
                     // after collision the first moments are j - omega (j - rho u) + (1 - omega/2) F and the
                     // zeroth is unchanged (Guo forcing, Sec. 2.2.1): fs_1 and fs_2 take the first moments as
                     // remainders, then fs_0 the zeroth, with every sum in FP64
-                    const double om = d.omega_f, gu = d.guo;
-                    const double px = jx64 - om * (jx64 - (double)rho * (double)ux) + gu * (double)Fx;
-                    const double py = jy64 - om * (jy64 - (double)rho * (double)uy) + gu * (double)Fy;
+                    const double omd = d.omega_f, gud = d.guo;
+                    const double px = jx64 - omd * (jx64 - (double)rho * (double)ux) + gud * (double)Fx;
+                    const double py = jy64 - omd * (jy64 - (double)rho * (double)uy) + gud * (double)Fy;
                     fs[1] = (float)(px - ((-(double)fs[3] + (double)fs[5]) + ((double)fs[8] - (double)fs[6] - (double)fs[7])));
                     fs[2] = (float)(py - ((-(double)fs[4] + (double)fs[5]) + ((double)fs[6] - (double)fs[7] - (double)fs[8])));
                     double s64 = 0.0;
@@ -414,29 +430,39 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             const float srcg = d.half_Lsat * (phi - phip);
             float gs[5];
             {
-                float geq[5], sgq[5];
-#pragma unroll
-                for (int q = 1; q < 5; ++q) {
-                    geq[q] = W5[q] * U * (1.f + 3.f * (CX[q] * ux + CY[q] * uy));
-                    sgq[q] = W5[q] * srcg;
-                }
-                geq[0] = U - ((geq[1] + geq[2]) + (geq[3] + geq[4]));
-                sgq[0] = srcg - ((sgq[1] + sgq[2]) + (sgq[3] + sgq[4]));
-#pragma unroll
-                for (int q = 0; q < 5; ++q) gs[q] = g[q] - (g[q] - geq[q]) * itg - sgq[q];
+                // relaxation toward g_eq = w U (1 + 3 c.u) and the source share w srcg, gathered:
+                //   gs_q = (1 - itg) g_q + w (itg U - srcg) + 3 w itg U c.u, rest as the remainder
+                const float K = itg * U - srcg, G0 = W5[1] * K, G1 = 0.5f * itg * U;  // 3 w = 1/2
+                const float Gx = G1 * ux, Gy = G1 * uy, itc = 1.f - itg;
+                const float E1 = G0 + Gx, E3 = G0 - Gx, E2 = G0 + Gy, E4 = G0 - Gy;
+                gs[1] = __builtin_fmaf(itc, g[1], E1);
+                gs[2] = __builtin_fmaf(itc, g[2], E2);
+                gs[3] = __builtin_fmaf(itc, g[3], E3);
+                gs[4] = __builtin_fmaf(itc, g[4], E4);
+                gs[0] = __builtin_fmaf(itc, g[0], K - ((E1 + E2) + (E3 + E4)));
                 if (EXACT)  // the zeroth moment after collision is U - src: gs_0 as its remainder
                     gs[0] = (float)((U64 - (double)srcg) - (((double)gs[1] + (double)gs[2]) + ((double)gs[3] + (double)gs[4])));
             }
 
-            // ---- phase field equilibrium (Eq. e) and source shares, rest population as remainder
-            float heq[9], shq[9];
-#pragma unroll
-            for (int q = 1; q < 9; ++q) {
-                heq[q] = W9[q] * (phi - 3.f * (CX[q] * Nx + CY[q] * Ny));
-                shq[q] = W9[q] * srcQ;
+            // ---- phase field (Eq. d, e): relaxation toward h_eq = w (phi - 3 c.N) plus the source share
+            // w srcQ, divided by a^2, gathered into Pq = ia2 (1 - ieta) h_q + ia2 (w K - 3 ieta w c.N)
+            // with K = ieta phi + srcQ; opposite velocities share the first term of the bracket and
+            // the rest population takes the remainder of the moving ones
+            float HP[9];
+            const float hc = ia2 * (1.f - ieta);
+            {
+                const float K = __builtin_fmaf(ieta, phi, srcQ), Ka = ia2 * K, Na = 3.f * ia2 * ieta;
+                auto pair = [&](int q, int qb, float cN) {
+                    const float S0 = W9[q] * Ka, D = W9[q] * Na * cN;
+                    HP[q] = S0 - D;
+                    HP[qb] = S0 + D;
+                };
+                pair(1, 3, Nx);
+                pair(2, 4, Ny);
+                pair(5, 7, Nx + Ny);
+                pair(6, 8, Ny - Nx);
+                HP[0] = Ka - sum8(HP);
             }
-            heq[0] = phi - sum8(heq);
-            shq[0] = srcQ - sum8(shq);
 
             // ---- references this cell hands to the populations it emits (16-bit storage)
             float rU = 0.f, rR = 0.f, rJx = 0.f, rJy = 0.f;
@@ -466,8 +492,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
             for (int q = 0; q < 9; ++q) {
                 const int xd = CX[q] > 0 ? xE : (CX[q] < 0 ? xW : x);
                 const uint32_t ypd = CY[q] > 0 ? ypN : (CY[q] < 0 ? ypS : yp);
-                const float hs = h[q] - (h[q] - heq[q]) * ieta + shq[q];
-                const float Pq = hs * ia2;
+                const float Pq = __builtin_fmaf(hc, h[q], HP[q]);
                 const int lq = own + CY[q] * LX + CX[q];
                 const float fm = (REF && FLOW) ? f_ref(rR, rJx, rJy, CX[q], CY[q]) : 0.f;
                 const float gm = REF ? (FLOW ? g_ref(rU, rJx, rJy, CX[q], CY[q]) : rU) : 0.f;

@@ -612,10 +612,12 @@ def test_c2_1024_full_length_crop_against_oracle():
 BF16_2048_MISS = pytest.mark.xfail(
     strict=False,
     reason="BF16 storage misses the 1e-2 phase-field target after 10^4 ventilated steps at 2048^2 "
-           "(1.4e-2 to 1.9e-2 measured on the moving interface, mean 1.3e-6): its 8-bit mantissa puts "
-           "rounding noise into every population at a level the run's own sensitivity amplifies to that "
-           "size; referencing h to its source cell's phi (1.44e-2) or g to the post-source vapour (1.85e-2) "
-           "did not close it.  FP16 meets the target.")
+           "(1.15e-2 against the oracle on the crop, 1.14e-2 against FP32 storage, on the moving interface; "
+           "mean 1.1e-6): its 8-bit mantissa puts rounding noise into every population at a level the "
+           "run's own sensitivity amplifies to that size.  Writing the flow collision as relaxation toward "
+           "a shifted target (well conditioned near equilibrium) brought it down from 1.5e-2; referencing "
+           "h to its source cell's phi (1.44e-2) or g to the post-source vapour (1.85e-2) did not close it.  "
+           "FP16 meets the target (4.3e-3).")
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", pytest.param("bf16", marks=BF16_2048_MISS)])
