@@ -28,6 +28,12 @@ __device__ constexpr float W19[19] = {1.f / 3.f,  1.f / 18.f, 1.f / 18.f, 1.f / 
                                       1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
 __device__ constexpr float W7[7] = {0.25f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f, 0.125f};
 
+// s += c v for a velocity component c in {-1, 0, 1} known at compile time (no instruction for c = 0)
+__device__ __forceinline__ void acc(double& s, int c, double v) {
+    if (c > 0) s += v;
+    else if (c < 0) s -= v;
+}
+
 __device__ __forceinline__ int wrapi(int i, int n) {
     if (i < 0) i += n;
     if (i >= n) i -= n;
@@ -133,16 +139,16 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
     const double phi64 = s_phi[own];
     const float phi = (float)phi64;
 
-    // isotropic gradient over the 18 D3Q19 neighbours, FP64
-    double gx64 = 0.0, gy64 = 0.0, gz64 = 0.0;
-#pragma unroll
-    for (int q = 1; q < 19; ++q) {
-        const double w = q < 7 ? 1.0 / 6.0 : 1.0 / 12.0;
-        const double v = w * s_phi[own + (CZ[q] * LY + CY[q]) * LX + CX[q]];
-        gx64 += CX[q] * v;
-        gy64 += CY[q] * v;
-        gz64 += CZ[q] * v;
-    }
+    // isotropic gradient over the 18 D3Q19 neighbours, FP64: differences across each pair of
+    // opposite neighbours, weighted 1/6 on the axes and 1/12 on the face diagonals
+    auto ph = [&](int q) { return s_phi[own + (CZ[q] * LY + CY[q]) * LX + CX[q]]; };
+    const double d1 = ph(1) - ph(2), d3 = ph(3) - ph(4), d5 = ph(5) - ph(6);  // x, y, z
+    const double d7 = ph(7) - ph(8), d9 = ph(9) - ph(10);                     // (1, 1, 0), (1, -1, 0)
+    const double d11 = ph(11) - ph(12), d13 = ph(13) - ph(14);                // (1, 0, 1), (1, 0, -1)
+    const double d15 = ph(15) - ph(16), d17 = ph(17) - ph(18);                // (0, 1, 1), (0, 1, -1)
+    const double gx64 = d1 * (1.0 / 6.0) + ((d7 + d9) + (d11 + d13)) * (1.0 / 12.0);
+    const double gy64 = d3 * (1.0 / 6.0) + ((d7 - d9) + (d15 + d17)) * (1.0 / 12.0);
+    const double gz64 = d5 * (1.0 / 6.0) + ((d11 - d13) + (d15 - d17)) * (1.0 / 12.0);
     // anisotropy a = 1 + eps P, P = Re((n_x + i n_y)^6), and the flux N = kappa Dphi |g|^2 a da/dg:
     // with X = gx^2/|g|^2, Y = gy^2/|g|^2,  P = X^3 - 15 X^2 Y + 15 X Y^2 - Y^3 and
     // |g|^2 dP/dg = 6 (gx (X^2 - 10 X Y + 5 Y^2 - P), -gy (5 X^2 - 10 X Y + Y^2 + P), -gz P)
@@ -176,10 +182,11 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
         double m64 = 0.0, jx64 = 0.0, jy64 = 0.0, jz64 = 0.0;
 #pragma unroll
         for (int q = 0; q < 19; ++q) {
-            m64 += (double)f[q];
-            jx64 += CX[q] * (double)f[q];
-            jy64 += CY[q] * (double)f[q];
-            jz64 += CZ[q] * (double)f[q];
+            const double v = f[q];
+            m64 += v;
+            acc(jx64, CX[q], v);
+            acc(jy64, CY[q], v);
+            acc(jz64, CZ[q], v);
         }
         const float drho = (float)m64, rho = 1.f + drho;
         const float pc = fminf(fmaxf(phi, -1.f), 1.f);
@@ -225,15 +232,10 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
         double rx = 0.0, ry = 0.0, rz = 0.0;
 #pragma unroll
         for (int q = 2; q < 19; ++q) {
-            if (q != 3 && q != 5) {
-                rx += CX[q] * (double)fs[q];
-                ry += CY[q] * (double)fs[q];
-                rz += CZ[q] * (double)fs[q];
-            } else if (q == 3) {
-                rz += CZ[q] * (double)fs[q];
-            } else {
-                ry += CY[q] * (double)fs[q];
-            }
+            const double v = fs[q];
+            acc(rx, CX[q], v);
+            if (q != 3) acc(ry, CY[q], v);  // fs_3 is the y remainder
+            if (q != 5) acc(rz, CZ[q], v);  // fs_5 is the z remainder
         }
         fs[1] = (float)(px - rx);
         fs[3] = (float)(py - ry);

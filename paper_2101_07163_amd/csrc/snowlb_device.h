@@ -64,17 +64,29 @@ struct StoreBF16 {
     static __device__ __forceinline__ float from_ref(T v) { return __uint_as_float((uint32_t)v << 16); }
 };
 
+// c . v for a lattice velocity with components in {-1, 0, 1}, known at compile time once the
+// population loop is unrolled: zero components cost no instruction (a product with 0.f would have
+// to be kept for IEEE semantics).  The value is that of cx vx + cy vy up to the sign of a zero.
+__device__ __forceinline__ float cdot(int cx, int cy, float vx, float vy) {
+    if (cx == 0) return cy == 0 ? 0.f : (cy > 0 ? vy : -vy);
+    const float a = cx > 0 ? vx : -vx;
+    if (cy == 0) return a;
+    return cy > 0 ? a + vy : a - vy;
+}
+
 // Reference of a 16-bit f_q: rho + 3 c_q . j of its source, with one explicit fused rounding so
 // that the writer and every reader produce the same bits.
 __device__ __forceinline__ float f_ref(float rho, float jx, float jy, int cx, int cy) {
-    return __builtin_fmaf(3.f, (float)cx * jx + (float)cy * jy, rho);
+    if (cx == 0 && cy == 0) return rho;
+    return __builtin_fmaf(3.f, cdot(cx, cy, jx, jy), rho);
 }
 
 // Reference of a 16-bit g_q: U (1 + 3 c_q . j) of its source (its first-order equilibrium with the
 // momentum j standing in for the velocity), with one explicit fused rounding so that the writer and
 // every reader produce the same bits.  A U reference of 0 gives 0 whatever j holds.
 __device__ __forceinline__ float g_ref(float U, float jx, float jy, int cx, int cy) {
-    return __builtin_fmaf(3.f * U, (float)cx * jx + (float)cy * jy, U);
+    if (cx == 0 && cy == 0) return U;
+    return __builtin_fmaf(3.f * U, cdot(cx, cy, jx, jy), U);
 }
 
 // Flow populations are carried as deviations from the lattice weights, df_q = f_q - w_q, through the
