@@ -188,14 +188,17 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
             acc(jy64, CY[q], v);
             acc(jz64, CZ[q], v);
         }
-        const float drho = (float)m64, rho = 1.f + drho;
-        const float pc = fminf(fmaxf(phi, -1.f), 1.f);
-        const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
-        const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
-        ux = (float)jx64 * sc;
-        uy = (float)jy64 * sc;
-        uz = (float)jz64 * sc;
-        const float Fx = -k * ux, Fy = -k * uy, Fz = -k * uz;
+        // drag and projected velocity in FP64 from the FP64 moments (in FP32, rho u would differ from j
+        // by a few ulps alike in every cell of a uniform stream, which the momentum closure below would
+        // apply as a force at every step)
+        const double rho64 = 1.0 + m64, pc64 = fmin(fmax(phi64, -1.0), 1.0);
+        const double k64 = (double)d.kdrag * (1.0 + pc64) * (1.0 + pc64) * (1.0 - pc64);
+        const double sc64 = 0.5 * (1.0 - pc64) / (rho64 + 0.5 * k64);
+        const double ux64 = jx64 * sc64, uy64 = jy64 * sc64, uz64 = jz64 * sc64;
+        const float drho = (float)m64, rho = (float)rho64, k = (float)k64;
+        ux = (float)ux64;
+        uy = (float)uy64;
+        uz = (float)uz64;
         const float uu = ux * ux + uy * uy + uz * uz;
         // BGK relaxation with the Guo term of F = -k u, as relaxation toward a shifted target:
         // fs_q = f_q - omega (f_q - T_q), T_q = f_eq,q - w_q + S_q / omega (exact in real arithmetic;
@@ -224,9 +227,9 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
         // is unchanged: fs_1, fs_3, fs_5 (+x, +y, +z) take the first moments as remainders, fs_0 the
         // zeroth, every sum in FP64
         const double omd = d.omega_f, gud = d.guo;
-        const double px = jx64 - omd * (jx64 - (double)rho * (double)ux) + gud * (double)Fx;
-        const double py = jy64 - omd * (jy64 - (double)rho * (double)uy) + gud * (double)Fy;
-        const double pz = jz64 - omd * (jz64 - (double)rho * (double)uz) + gud * (double)Fz;
+        const double px = jx64 - omd * (jx64 - rho64 * ux64) - gud * k64 * ux64;
+        const double py = jy64 - omd * (jy64 - rho64 * uy64) - gud * k64 * uy64;
+        const double pz = jz64 - omd * (jz64 - rho64 * uz64) - gud * k64 * uz64;
         // the other populations' shares of each first moment (fs_1, fs_3 and fs_5 carry momentum along
         // their own axis only, so the three remainders are independent)
         double rx = 0.0, ry = 0.0, rz = 0.0;

@@ -375,13 +375,32 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                     jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
                     jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
                 }
-                rho = 1.f + drho;
-                const float pc = fminf(fmaxf(phi, -1.f), 1.f);
-                const float k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
-                const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
-                ux = jx * sc;
-                uy = jy * sc;
-                const float Fx = -k * ux, Fy = -k * uy;
+                // drag k = h eta_f (1 + phi)^2 (1 - phi) / (4 W0^2) and the projected velocity
+                // u = (1 - phi)/2 j / (rho + k/2).  FP32 storage takes this chain in FP64 from the FP64
+                // moments: in FP32, rho u differs from j by a few ulps, by the same amount in every cell
+                // of a uniform stream, and the momentum closure below would apply that difference as a
+                // force on the whole stream at every step
+                float k;
+                double rho64 = 0.0, k64 = 0.0, ux64 = 0.0, uy64 = 0.0;
+                if (EXACT) {
+                    rho64 = 1.0 + m64;
+                    const double pc64 = fmin(fmax(phi64, -1.0), 1.0);
+                    k64 = (double)d.kdrag * (1.0 + pc64) * (1.0 + pc64) * (1.0 - pc64);
+                    const double sc64 = 0.5 * (1.0 - pc64) / (rho64 + 0.5 * k64);
+                    ux64 = jx64 * sc64;
+                    uy64 = jy64 * sc64;
+                    rho = (float)rho64;
+                    k = (float)k64;
+                    ux = (float)ux64;
+                    uy = (float)uy64;
+                } else {
+                    rho = 1.f + drho;
+                    const float pc = fminf(fmaxf(phi, -1.f), 1.f);
+                    k = d.kdrag * (1.f + pc) * (1.f + pc) * (1.f - pc);
+                    const float sc = 0.5f * (1.f - pc) / (rho + 0.5f * k);
+                    ux = jx * sc;
+                    uy = jy * sc;
+                }
                 const float uu = ux * ux + uy * uy;
                 // BGK relaxation with the Guo term of F = -k u, written as relaxation toward a shifted
                 // target: fs_q = f_q - omega (f_q - T_q) with T_q = f_eq,q - w_q + S_q / omega (exact in
@@ -412,8 +431,8 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
                     // zeroth is unchanged (Guo forcing, Sec. 2.2.1): fs_1 and fs_2 take the first moments as
                     // remainders, then fs_0 the zeroth, with every sum in FP64
                     const double omd = d.omega_f, gud = d.guo;
-                    const double px = jx64 - omd * (jx64 - (double)rho * (double)ux) + gud * (double)Fx;
-                    const double py = jy64 - omd * (jy64 - (double)rho * (double)uy) + gud * (double)Fy;
+                    const double px = jx64 - omd * (jx64 - rho64 * ux64) - gud * k64 * ux64;
+                    const double py = jy64 - omd * (jy64 - rho64 * uy64) - gud * k64 * uy64;
                     fs[1] = (float)(px - ((-(double)fs[3] + (double)fs[5]) + ((double)fs[8] - (double)fs[6] - (double)fs[7])));
                     fs[2] = (float)(py - ((-(double)fs[4] + (double)fs[5]) + ((double)fs[6] - (double)fs[7] - (double)fs[8])));
                     double s64 = 0.0;

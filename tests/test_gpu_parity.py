@@ -541,9 +541,10 @@ def test_half_storage_c1_plain_128(storage):
 def test_ventilated_512_long_run(storage):
     """The 2048^2 half-storage workload's physics (inlet u = 0.01, U_in = U0 = 0.6, seed R = 8) on a
     512^2 lattice with the seed at (150, 256), 10000 steps, against the FP64 oracle.  Errors per
-    field are printed; the phase field bar is 1e-2 for FP16 and BF16 storage.  FP32 storage is held to
-    the derived bar max(1e-4, 2 x the oracle's own spread under one-ulp noise per step), with 1e-3 as a
-    hard regression guard."""
+    field are printed; the phase field bar is 1e-2 for FP16 and BF16 storage and the 1e-4 target for
+    FP32 storage (2.6e-5 measured; 4.8e-4 while the projected velocity was formed in FP32, whose
+    rounding bias acted as a force on the uniform stream through the momentum closure).  The derived
+    bar, twice the oracle's own spread under one-ulp noise per step, is printed beside it."""
     cfg = dict(W.C3)
     cfg.update(nx=512, ny=512, seed=(150.0, 256.0, 8.0))
     o = _ventilated_512_oracle(cfg)
@@ -553,14 +554,10 @@ def test_ventilated_512_long_run(storage):
     for k, v in errs.items():
         report("512^2 10k %s %s" % (storage, k), v)
     if storage == "fp32":
-        assert errs["phi"] <= 1e-3  # regression guard
         bar = derived_bar("v512", 10000)
         assert bar is not None
-        print("  512^2 10k fp32 phi %.3e against the derived bar %.3e" % (errs["phi"], bar), flush=True)
-        if errs["phi"] > bar:
-            pytest.xfail("FP32 phase field %.2e after 10^4 steps at 512^2 exceeds twice the FP64 oracle's own "
-                         "spread under one-ulp noise per step (bar %.2e): the FP32 run carries an error "
-                         "component beyond that sensitivity, not found" % (errs["phi"], bar))
+        print("  512^2 10k fp32 phi %.3e (target 1e-4; derived bar %.3e)" % (errs["phi"], bar), flush=True)
+        assert errs["phi"] <= 1e-4
     else:
         assert errs["phi"] <= 1e-2
 
@@ -587,11 +584,10 @@ GOLDEN_C2 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "
 def test_c2_1024_full_length_crop_against_oracle():
     """The 1024^2 ventilated workload over its full 2*10^4 steps in FP32 storage against the FP64
     oracle's fields after the same run, on the 512^2 crop around the crystal (rows 256..767, columns
-    44..555), stored by tests/golden/make_oracle_crop.py.  Measured: phase field 2.0e-3, U 2.6e-4,
-    rho 1.3e-5, u 7.7e-6.  The bar is derived: max(1e-4, 2 x the FP64 oracle's own spread at 2*10^4
-    steps under one-ulp noise per value and step), stored by tests/golden/make_oracle_spread.py (the
-    spread is 2.2e-3 there, 1.9e-4 at 10^4 steps): at this length the run's own sensitivity, not the
-    kernel, sets the error."""
+    44..555), stored by tests/golden/make_oracle_crop.py.  Measured: phase field 3.5e-4.  The bar is
+    derived: max(1e-4, 2 x the FP64 oracle's own spread at 2*10^4 steps under one-ulp noise per value
+    and step), stored by tests/golden/make_oracle_spread.py (the spread is 2.2e-3 there, 1.9e-4 at 10^4
+    steps): at this length the run's own sensitivity, not the kernel, sets the error."""
     data = np.load(GOLDEN_C2)
     cfg = W.C2
     (r0, r1), (c0, c1) = [tuple(int(v) for v in data["rows"]), tuple(int(v) for v in data["cols"])]
@@ -625,9 +621,8 @@ def test_c3_2048_crop_against_oracle(storage):
     """The half-storage workload at its own size against the FP64 oracle: the 2048^2 ventilated
     lattice over its 10^4 steps in each storage format, compared on the 512^2 crop around the crystal
     (rows 768..1279, columns 44..555) with the oracle's fields after the same run, stored (rounded to
-    float32) by tests/golden/make_oracle_crop.py.  FP32 is held to the derived bar max(1e-4, 2 x the
-    oracle's own spread) where the spread of this run is stored, else to 1e-3; FP16 and BF16 to the
-    1e-2 half-storage target."""
+    float32) by tests/golden/make_oracle_crop.py.  FP32 is held to the 1e-4 target (2.6e-5 measured),
+    FP16 and BF16 to the 1e-2 half-storage target."""
     data = np.load(GOLDEN_C3)
     cfg = W.C3
     (r0, r1), (c0, c1) = cfg["crop"]
@@ -641,10 +636,10 @@ def test_c3_2048_crop_against_oracle(storage):
         report("2048^2 crop 10k %s %s" % (storage, k), errs[k])
     del sim
     torch.cuda.empty_cache()
-    bar = {"fp32": 1e-3, "fp16": 1e-2, "bf16": 1e-2}[storage]
+    bar = {"fp32": 1e-4, "fp16": 1e-2, "bf16": 1e-2}[storage]
     if storage == "fp32" and derived_bar("c3", 10000) is not None:
-        bar = derived_bar("c3", 10000)
-        print("  2048^2 crop 10k fp32 phi %.3e against the derived bar %.3e" % (errs["phi"], bar), flush=True)
+        print("  2048^2 crop 10k fp32 phi %.3e (target 1e-4; derived bar %.3e)" % (errs["phi"], derived_bar("c3", 10000)),
+              flush=True)
     assert errs["phi"] <= bar
 
 
@@ -683,7 +678,8 @@ def test_c2_ventilated_1024_checkpoints():
     """The 1024^2 ventilated workload (inlet u = 0.02, U_in = U0 = 0.6, seed R = 8 at (300, 512),
     tau_f = 0.6, tau_vap = 0.8) in FP32 storage against the FP64 oracle at checkpoints 1000 and 5000
     steps; the error of every field is printed at each checkpoint.  The phase field is held to 1e-4
-    at both (7e-5 measured at 5000 steps, with the collision's moments closed in FP64; 2.2e-4 without).
+    at both (1.1e-5 measured at 5000 steps; 7.2e-5 with the projected velocity formed in FP32, 2.2e-4
+    without the collision's moments closed in FP64).
     About 6e9 oracle updates."""
     cfg = W.C2
     o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
