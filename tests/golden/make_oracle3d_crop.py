@@ -2,7 +2,7 @@
 inlet u = 0.01, seed R = 8, 2000 steps), on the box around the crystal (phi > -0.9, widened by 8 cells),
 rounded to float32; the GPU test compares the same box of its own run:
 
-    python tests/golden/make_oracle3d_crop.py   # -> f4_crop_2000.npz
+    python tests/golden/make_oracle3d_crop.py [out.npz]   # default: tests/golden/f4_crop_2000.npz
 
 It calls only the oracle (about 20 minutes on 8 cores).
 """
@@ -23,7 +23,7 @@ OUT = os.path.join(HERE, "f4_crop_2000.npz")
 PAD = 8
 
 
-def main() -> None:
+def main(out: str = OUT) -> None:
     cfg = W.F4_3D
     steps = cfg["steps"]
     o = oracle.Oracle3D(oracle.Params3D.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"])
@@ -40,9 +40,9 @@ def main() -> None:
     box = [(max(0, int(a.min()) - PAD), min(n, int(a.max()) + 1 + PAD)) for a, n in ((zs, nz), (ys, ny), (xs, nx))]
     (z0, z1), (y0, y1), (x0, x1) = box
     arrays = {k: F[k][z0:z1, y0:y1, x0:x1].astype(np.float32) for k in ("phi", "U", "ux")}
-    np.savez_compressed(OUT, steps=np.int64(steps), box=np.array(box, dtype=np.int64), **arrays)
-    print("wrote", OUT, "box", box, flush=True)
+    np.savez_compressed(out, steps=np.int64(steps), box=np.array(box, dtype=np.int64), **arrays)
+    print("wrote", out, "box", box, flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(*sys.argv[1:2])

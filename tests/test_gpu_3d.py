@@ -1,6 +1,8 @@
 """The 3D step on the GPU (include/snowlb3d.h) against the 3D FP64 oracle: one step from arbitrary
 states on ragged and degenerate lattices, every closure; seed growth and a ventilated crystal over
 hundreds of steps; FP64 diagnostics against host sums; graph replay against single launches."""
+import os
+
 import numpy as np
 import pytest
 
@@ -145,3 +147,23 @@ def test_f4_workload_full_size_first_steps():
             err = float(np.abs(got[b] - F[k][b]).max())
             report("F4 full size 10 steps %s %s" % (name, k), err)
             assert err <= 1e-5, (k, name, err)
+
+
+GOLDEN_F4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "f4_crop_2000.npz")
+
+
+def test_f4_workload_full_run_against_stored_oracle():
+    """The 3D benchmark workload over its full 2000 steps (256 x 128 x 128 ventilated) against the FP64
+    oracle's fields after the same run, on the box around the crystal, stored (rounded to float32) by
+    tests/golden/make_oracle3d_crop.py: phase field within the 1e-4 FP32 target, U and u_x printed."""
+    data = np.load(GOLDEN_F4)
+    cfg = W.F4_3D
+    assert int(data["steps"]) == cfg["steps"] == 2000
+    (z0, z1), (y0, y1), (x0, x1) = (tuple(int(v) for v in r) for r in data["box"])
+    sim = S.Sim3D(cfg).init().step(cfg["steps"])
+    errs = {}
+    for k in ("phi", "U", "ux"):
+        got = sim.read(k)[z0:z1, y0:y1, x0:x1].double().cpu().numpy()
+        errs[k] = float(np.abs(got - data[k].astype(np.float64)).max())
+        report("F4 full run 2000 steps %s" % k, errs[k])
+    assert errs["phi"] <= 1e-4, errs
