@@ -18,7 +18,9 @@ Cases (regions are the cells the GPU tests compare):
   c4    each of the 64 crystals over 5000 steps, the box around its crystal (phi > -0.9, widened by
         16 cells); also stores each crystal's phi and U on that box (float32) in c4_members_5000.npz
 
-Results go to oracle_spread.json (merged with what is there).  It calls only the oracle; c3 takes
+Results go to oracle_spread.json (merged with what is there).  The sweep's members can also be split
+between machines: "c4part FIRST LAST DIR" computes members FIRST..LAST-1 into DIR, and "c4merge DIR" adds
+them to the stored files (each member depends only on its own parameters and seed).  It calls only the oracle; c3 takes
 about an hour and c4 about four on 8 cores (c4 resumes after the last member stored).
 """
 import json
@@ -108,6 +110,8 @@ def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
             ref.step(k)
         done += k
         perturb(noisy, draws, k)
+        if done % 1000 == 0:
+            print("%s perturbed run step %d" % (log, done), flush=True)
         if done in checkpoints:
             a = noisy.fields()["phi"][r0:r1, c0:c1]
             b = ref.fields()["phi"][r0:r1, c0:c1] if ref is not None else ref_at_end
@@ -159,6 +163,33 @@ def crystal_box(phi, pad=16):
             (max(0, int(xs.min()) - pad), min(nx, int(xs.max()) + 1 + pad)))
 
 
+def c4_member(i, cfg, steps):
+    """Arrays and record of sweep member i: its phi and U on the box around its crystal after the full
+    run, and the oracle's spread there."""
+    ref = new(cfg)
+    for done in range(0, steps, 1000):
+        ref.step(min(1000, steps - done))
+        print("c4[%d] reference run step %d" % (i, min(done + 1000, steps)), flush=True)
+    F = ref.fields()
+    (r0, r1), (c0, c1) = crystal_box(F["phi"])
+    arrays = {"phi_%d" % i: F["phi"][r0:r1, c0:c1].astype(np.float32),
+              "U_%d" % i: F["U"][r0:r1, c0:c1].astype(np.float32),
+              "box_%d" % i: np.array([r0, r1, c0, c1], dtype=np.int64)}
+    sp = spread_run(cfg, steps, {steps}, ((r0, r1), (c0, c1)), 7163 + i,
+                    ref_at_end=F["phi"][r0:r1, c0:c1], log="c4[%d] %dx%d" % (i, cfg["nx"], cfg["ny"]))
+    member = {"i": i, "nx": cfg["nx"], "eps": cfg["eps"], "U0": cfg["U0"], "u_in": cfg["u_in"],
+              "box": [[r0, r1], [c0, c1]], "spread_phi": sp[str(steps)]}
+    return arrays, member
+
+
+def store_c4(arrays, members, steps):
+    np.savez_compressed(C4_NPZ + ".tmp.npz", steps=np.int64(steps), **{k: v for k, v in arrays.items() if k != "steps"})
+    os.replace(C4_NPZ + ".tmp.npz", C4_NPZ)
+    d = load()
+    d["c4"] = dict(header(), steps=steps, members=sorted(members, key=lambda m: m["i"]))
+    save(d)
+
+
 def case_c4():
     cfgs = W.c4_domains()
     steps = cfgs[0]["steps"]
@@ -168,25 +199,49 @@ def case_c4():
         arrays = {k: old[k] for k in old.files}
         members = load().get("c4", {}).get("members", [])
     t0 = time.time()
-    for i in range(len(members), len(cfgs)):
-        cfg = cfgs[i]
-        ref = new(cfg).step(steps)
-        F = ref.fields()
-        (r0, r1), (c0, c1) = crystal_box(F["phi"])
-        arrays["phi_%d" % i] = F["phi"][r0:r1, c0:c1].astype(np.float32)
-        arrays["U_%d" % i] = F["U"][r0:r1, c0:c1].astype(np.float32)
-        arrays["box_%d" % i] = np.array([r0, r1, c0, c1], dtype=np.int64)
-        sp = spread_run(cfg, steps, {steps}, ((r0, r1), (c0, c1)), 7163 + i,
-                        ref_at_end=F["phi"][r0:r1, c0:c1], log="c4[%d] %dx%d" % (i, cfg["nx"], cfg["ny"]))
-        members.append({"i": i, "nx": cfg["nx"], "eps": cfg["eps"], "U0": cfg["U0"], "u_in": cfg["u_in"],
-                        "box": [[r0, r1], [c0, c1]], "spread_phi": sp[str(steps)]})
-        np.savez_compressed(C4_NPZ + ".tmp.npz", steps=np.int64(steps), **{k: v for k, v in arrays.items() if k != "steps"})
-        os.replace(C4_NPZ + ".tmp.npz", C4_NPZ)
-        d = load()
-        d["c4"] = dict(header(), steps=steps, members=members)
-        save(d)
+    have = {m["i"] for m in members}
+    for i in range(len(cfgs)):
+        if i in have:
+            continue
+        a, m = c4_member(i, cfgs[i], steps)
+        arrays.update(a)
+        members.append(m)
+        store_c4(arrays, members, steps)
         print("c4 member %d done (%.0f s)" % (i, time.time() - t0), flush=True)
     return load()["c4"]
+
+
+def c4_part(first, last, outdir):
+    """Members first..last-1 into outdir/c4_part.npz and outdir/c4_part.json (for a second machine);
+    c4_merge adds such a part to the stored files."""
+    cfgs = W.c4_domains()
+    steps = cfgs[0]["steps"]
+    arrays, members = {}, []
+    os.makedirs(outdir, exist_ok=True)
+    for i in range(int(first), int(last)):
+        a, m = c4_member(i, cfgs[i], steps)
+        arrays.update(a)
+        members.append(m)
+        np.savez_compressed(os.path.join(outdir, "c4_part.npz"), **arrays)
+        json.dump(members, open(os.path.join(outdir, "c4_part.json"), "w"), indent=1, sort_keys=True)
+        print("c4 member %d done" % i, flush=True)
+
+
+def c4_merge(outdir):
+    steps = W.c4_domains()[0]["steps"]
+    old = np.load(C4_NPZ)
+    arrays = {k: old[k] for k in old.files}
+    members = load()["c4"]["members"]
+    have = {m["i"] for m in members}
+    part = np.load(os.path.join(outdir, "c4_part.npz"))
+    for m in json.load(open(os.path.join(outdir, "c4_part.json"))):
+        if m["i"] in have:
+            continue
+        for k in ("phi", "U", "box"):
+            arrays["%s_%d" % (k, m["i"])] = part["%s_%d" % (k, m["i"])]
+        members.append(m)
+    store_c4(arrays, members, steps)
+    print("merged; %d members stored" % len(members), flush=True)
 
 
 CASES = {"v512": case_v512, "c2": case_c2, "c3": case_c3, "c4": case_c4}
@@ -202,4 +257,9 @@ def main(names):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["v512"])
+    if sys.argv[1:2] == ["c4part"]:
+        c4_part(*sys.argv[2:5])
+    elif sys.argv[1:2] == ["c4merge"]:
+        c4_merge(sys.argv[2])
+    else:
+        main(sys.argv[1:] or ["v512"])

@@ -1,7 +1,10 @@
 """Batched crystals: one launch per step over the tiles of many uneven domains.  Each domain must
 evolve bitwise as a solo run of the same parameters (same kernel, same per-domain arithmetic), in
-every tile shape and grid mode, through graph replays; one member is also checked against the FP64
-oracle."""
+every tile shape and grid mode, through graph replays; every member of the 64-crystal sweep is also
+checked against the FP64 oracle's fields after its full run."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -129,29 +132,60 @@ def test_batched_no_flow_periodic():
         assert np.abs(b.read(2, k).double().cpu().numpy() - F[k]).max() < 1e-5, k
 
 
+GOLDEN_C4 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_members_5000.npz")
+SPREAD_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_spread.json")
+
+
 def test_c4_sweep_full_length():
-    """The 64-crystal sweep over its full 5000 steps in one batch: every crystal finite; a 256^2 member
-    (eps 0.052, U0 0.51, u_in 0.0018) against the FP64 oracle, phase field within 1e-4; two members
-    bitwise equal to solo runs.  Not every member can be held to 1e-4 after 5000 steps: for the
-    fastest-growing, most anisotropic one (member 22: eps 0.078, U0 0.68) relative perturbations of
-    3e-7 applied to the FP64 oracle's own state every 10 steps move its phase field by 2.4e-2, and
-    the FP32 run differs from the oracle by 1.0e-3; the member used here moves by 3e-6 under the same
-    perturbations."""
+    """The 64-crystal sweep over its full 5000 steps in one batch: every crystal finite, and every one
+    against the FP64 oracle's fields after the same run, on the box around its crystal (stored with the
+    oracle's own spread by tests/golden/make_oracle_spread.py).  Each member's phase field is held to
+    its derived bar max(1e-4, 2 x the oracle's spread under one-ulp noise per value and step): the 1e-4
+    target wherever the crystal's own sensitivity allows it (35 of the 64 members).  The fastest-growing
+    crystals (U0 near 0.9) are so sensitive that the oracle's own spread exceeds 1e-2 for 8 members and
+    reaches 2 for two of them (a side branch forms in one run and not in the other): for those the
+    pointwise comparison after 5000 steps carries no information, and their crystal areas (cells with
+    phi > 0 on the box) are printed beside the oracle's.  Two members are also bitwise equal to solo
+    runs.  Members whose oracle fields are not stored yet (the script resumes member by member)
+    are listed; member 13 (256^2, eps 0.052, U0 0.51) is then run on the oracle here and held to 1e-4."""
     cfgs = W.c4_domains()
     steps = cfgs[0]["steps"]
+    data = np.load(GOLDEN_C4)
+    members = {m["i"]: m for m in json.load(open(SPREAD_JSON))["c4"]["members"]}
+    assert int(data["steps"]) == steps and set(members) <= set(range(len(cfgs)))
+    assert all("phi_%d" % i in data.files for i in members)
+    missing = [i for i in range(len(cfgs)) if i not in members]
+    if missing:
+        print("  c4: oracle fields not stored for %d of %d members" % (len(missing), len(cfgs)), flush=True)
     b = S.Batch(cfgs).init().step(steps)
     torch.cuda.synchronize()
-    for i in range(len(cfgs)):
+    worst = []
+    for i, cfg in enumerate(cfgs):
         d = b.diag(i)
         assert d["status"] == S.OK and d["n_nonfinite"] == 0, i
-    i = 13
-    cfg = cfgs[i]
-    assert cfg["nx"] == 256 and abs(cfg["eps"] - 0.052) < 1e-3
-    o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"]).step(steps)
-    F = o.fields()
-    errs = {k: float(np.abs(b.read(i, k).double().cpu().numpy() - F[k]).max()) for k in ("phi", "U", "rho", "ux", "uy")}
-    print("  c4 member %d (256^2) after %d steps: %s" % (i, steps, {k: "%.2e" % v for k, v in errs.items()}), flush=True)
-    assert errs["phi"] <= 1e-4, errs
+        if i not in members:
+            continue
+        r0, r1, c0, c1 = (int(v) for v in data["box_%d" % i])
+        m = members[i]
+        assert [[r0, r1], [c0, c1]] == m["box"] and m["nx"] == cfg["nx"]
+        got = {k: b.read(i, k)[r0:r1, c0:c1].double().cpu().numpy() for k in ("phi", "U")}
+        e_phi = float(np.abs(got["phi"] - data["phi_%d" % i].astype(np.float64)).max())
+        e_U = float(np.abs(got["U"] - data["U_%d" % i].astype(np.float64)).max())
+        bar = max(1e-4, 2.0 * m["spread_phi"])
+        worst.append((e_phi / bar, i))
+        area = "area %d / %d" % (int((got["phi"] > 0).sum()), int((data["phi_%d" % i] > 0).sum()))
+        print("  c4 member %2d %4d^2 eps %.3f U0 %.2f u_in %.4f: phi %.2e (spread %.2e, bar %.2e)  U %.2e  %s" % (
+            i, cfg["nx"], cfg["eps"], cfg["U0"], cfg["u_in"], e_phi, m["spread_phi"], bar, e_U, area), flush=True)
+        assert e_phi <= bar, (i, e_phi, bar)
+    if worst:
+        print("  c4: largest error / bar %.2f (member %d)" % max(worst), flush=True)
+    if 13 in missing:
+        cfg = cfgs[13]
+        assert cfg["nx"] == 256 and abs(cfg["eps"] - 0.052) < 1e-3
+        o = oracle.Oracle(oracle.Params.from_dict(cfg)).init_seed(*cfg["seed"], cfg["w_init"], cfg["U0"]).step(steps)
+        e = float(np.abs(b.read(13, "phi").double().cpu().numpy() - o.fields()["phi"]).max())
+        print("  c4 member 13 (256^2) against the oracle run here: phi %.2e" % e, flush=True)
+        assert e <= 1e-4
     for j in (4, 63):
         solo = S.Sim(cfgs[j]).init().step(steps)
         for k in ("phi", "U", "ux"):
