@@ -20,7 +20,9 @@ Cases (regions are the cells the GPU tests compare):
 
 Results go to oracle_spread.json (merged with what is there).  The sweep's members can also be split
 between machines: "c4part FIRST LAST DIR" computes members FIRST..LAST-1 into DIR, and "c4merge DIR" adds
-them to the stored files (each member depends only on its own parameters and seed).  It calls only the oracle; c3 takes
+them to the stored files (each member depends only on its own parameters and seed); "c4areas DIR"
+records, for the members whose spread exceeds 1e-2, the crystal areas of the reference and perturbed
+runs, which c4merge adds as well.  It calls only the oracle; c3 takes
 about an hour and c4 about four on 8 cores (c4 resumes after the last member stored).
 """
 import json
@@ -94,9 +96,10 @@ def perturb(o, draws, k):
     o.set_state(**s)
 
 
-def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
+def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log="", keep=None):
     """phi spread at each checkpoint over region ((r0, r1), (c0, c1)); the reference runs alongside
-    unless its phi on the region at the last checkpoint is given (ref_at_end)."""
+    unless its phi on the region at the last checkpoint is given (ref_at_end).  keep (a dict), if
+    given, receives the perturbed run's phi on the region at the last checkpoint."""
     (r0, r1), (c0, c1) = region
     noisy = new(cfg)
     draws = Draws(noisy, np.random.default_rng(seed))
@@ -116,6 +119,8 @@ def spread_run(cfg, steps, checkpoints, region, seed, ref_at_end=None, log=""):
             a = noisy.fields()["phi"][r0:r1, c0:c1]
             b = ref.fields()["phi"][r0:r1, c0:c1] if ref is not None else ref_at_end
             out[str(done)] = float(np.abs(a - b).max())
+            if keep is not None:
+                keep["phi"] = a.copy()
             print("%s step %d spread %.3e (%.0f s)" % (log, done, out[str(done)], time.time() - t0), flush=True)
     draws.close()
     return out
@@ -211,6 +216,34 @@ def case_c4():
     return load()["c4"]
 
 
+def c4_areas(outdir, *only, threshold=1e-2):
+    """For the sweep members whose stored spread exceeds threshold (their phase field after 5000 steps
+    is not reproducible pointwise under one-ulp noise): the crystal area (cells with phi > 0 on the
+    stored box) of the reference run and of the same perturbed run as the spread's, into
+    outdir/c4_areas.json; c4_merge adds them to the stored records."""
+    cfgs = W.c4_domains()
+    steps = cfgs[0]["steps"]
+    os.makedirs(outdir, exist_ok=True)
+    out = {}
+    for m in load()["c4"]["members"]:
+        if m["spread_phi"] <= threshold or (only and str(m["i"]) not in only):
+            continue
+        i = m["i"]
+        (r0, r1), (c0, c1) = m["box"]
+        ref = new(cfgs[i])
+        for done in range(0, steps, 1000):
+            ref.step(min(1000, steps - done))
+            print("c4[%d] reference run step %d" % (i, min(done + 1000, steps)), flush=True)
+        phi = ref.fields()["phi"][r0:r1, c0:c1]
+        keep = {}
+        spread_run(cfgs[i], steps, {steps}, ((r0, r1), (c0, c1)), 7163 + i, ref_at_end=phi,
+                   log="c4[%d] area" % i, keep=keep)
+        out[str(i)] = [int((phi > 0).sum()), int((keep["phi"] > 0).sum())]
+        json.dump(out, open(os.path.join(outdir, "c4_areas%s.json" % ("_" + "_".join(only) if only else "")), "w"),
+                  indent=1, sort_keys=True)
+        print("c4 member %d areas %s" % (i, out[str(i)]), flush=True)
+
+
 def c4_part(first, last, outdir):
     """Members first..last-1 into outdir/c4_part.npz and outdir/c4_part.json (for a second machine);
     c4_merge adds such a part to the stored files."""
@@ -233,8 +266,17 @@ def c4_merge(outdir):
     arrays = {k: old[k] for k in old.files}
     members = load()["c4"]["members"]
     have = {m["i"] for m in members}
-    part = np.load(os.path.join(outdir, "c4_part.npz"))
-    for m in json.load(open(os.path.join(outdir, "c4_part.json"))):
+    areas = {}
+    for f in sorted(os.listdir(outdir)):
+        if f.startswith("c4_areas") and f.endswith(".json"):
+            areas.update(json.load(open(os.path.join(outdir, f))))
+    if areas:
+        for m in members:
+            if str(m["i"]) in areas:
+                m["area_ref"], m["area_perturbed"] = areas[str(m["i"])]
+    part_file = os.path.join(outdir, "c4_part.json")
+    part = np.load(os.path.join(outdir, "c4_part.npz")) if os.path.exists(part_file) else None
+    for m in (json.load(open(part_file)) if part is not None else []):
         if m["i"] in have:
             continue
         for k in ("phi", "U", "box"):
@@ -259,6 +301,8 @@ def main(names):
 if __name__ == "__main__":
     if sys.argv[1:2] == ["c4part"]:
         c4_part(*sys.argv[2:5])
+    elif sys.argv[1:2] == ["c4areas"]:
+        c4_areas(*sys.argv[2:])
     elif sys.argv[1:2] == ["c4merge"]:
         c4_merge(sys.argv[2])
     else:

@@ -105,3 +105,5 @@ def test_stored_oracle_spreads_match_their_recipe():
                 a = arrays["%s_%d" % (k, i)]
                 assert a.shape == (r1 - r0, c1 - c0) and a.dtype == np.float32 and np.isfinite(a).all()
             assert m["spread_phi"] > 0
+            if m["spread_phi"] > 1e-2:  # the chaotic members also carry their crystal areas
+                assert m["area_ref"] == int((arrays["phi_%d" % i] > 0).sum()) and m["area_perturbed"] > 0

@@ -144,9 +144,9 @@ def test_c4_sweep_full_length():
     target wherever the crystal's own sensitivity allows it (35 of the 64 members).  The fastest-growing
     crystals (U0 near 0.9) are so sensitive that the oracle's own spread exceeds 1e-2 for 8 members and
     reaches 2 for two of them (a side branch forms in one run and not in the other): for those the
-    pointwise comparison after 5000 steps carries no information, and their crystal areas (cells with
-    phi > 0 on the box) are printed beside the oracle's.  Two members are also bitwise equal to solo
-    runs.  Members whose oracle fields are not stored yet (the script resumes member by member)
+    pointwise comparison after 5000 steps carries no information, and their crystal area (cells with
+    phi > 0 on the box) is held instead to max(1, 2 x how far the oracle's own perturbed run moved it),
+    also stored by the script.  Two members are also bitwise equal to solo runs.  Members whose oracle fields are not stored yet (the script resumes member by member)
     are listed; member 13 (256^2, eps 0.052, U0 0.51) is then run on the oracle here and held to 1e-4."""
     cfgs = W.c4_domains()
     steps = cfgs[0]["steps"]
@@ -177,6 +177,13 @@ def test_c4_sweep_full_length():
         print("  c4 member %2d %4d^2 eps %.3f U0 %.2f u_in %.4f: phi %.2e (spread %.2e, bar %.2e)  U %.2e  %s" % (
             i, cfg["nx"], cfg["eps"], cfg["U0"], cfg["u_in"], e_phi, m["spread_phi"], bar, e_U, area), flush=True)
         assert e_phi <= bar, (i, e_phi, bar)
+        if "area_ref" in m:
+            a_gpu, a_ref = int((got["phi"] > 0).sum()), m["area_ref"]
+            assert a_ref == int((data["phi_%d" % i] > 0).sum())
+            a_bar = max(1, 2 * abs(m["area_perturbed"] - a_ref))
+            print("  c4 member %2d crystal area %d against the oracle's %d (bar %d cells)" % (i, a_gpu, a_ref, a_bar),
+                  flush=True)
+            assert abs(a_gpu - a_ref) <= a_bar, (i, a_gpu, a_ref, a_bar)
     if worst:
         print("  c4: largest error / bar %.2f (member %d)" % max(worst), flush=True)
     if 13 in missing:
