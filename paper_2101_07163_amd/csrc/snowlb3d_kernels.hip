@@ -82,9 +82,15 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
 
     const int tid = threadIdx.x;
     const int tx = tid & (kBX - 1), ty = (tid >> kSX) & (kBY - 1), tz = tid >> (kSX + kSY);
-    // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid)
+    // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid),
+    // walked backwards every other step (input copy 1), so that a step starts on the blocks the
+    // previous one wrote last, which are still in the last-level cache
     const int G = gridDim.x, b = blockIdx.x;
-    const int t = xcd_remap ? (b % 8) * (G / 8) + min(b % 8, G % 8) + b / 8 : b;
+    int t = b;
+    if (xcd_remap) {
+        const int x = b % 8, k = b / 8, cnt = G / 8 + (x < G % 8 ? 1 : 0);
+        t = x * (G / 8) + min(x, G % 8) + (par ? cnt - 1 - k : k);
+    }
     const int bx = t % d.nbx, by = (t / d.nbx) % d.nby, bz = t / (d.nbx * d.nby);
     const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
     const int x = x0 + tx, y = y0 + ty, z = z0 + tz;

@@ -90,10 +90,16 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
     // XCD-aware order (optional): consecutive workgroup ids are spread over the 8 XCDs; give each
     // XCD a contiguous run of tiles so neighbouring tiles share halo lines in that XCD's L2.  XCD x
     // receives G/8 workgroups, one more for x < G % 8; its runs follow each other in x order, so the
-    // mapping is a permutation of the grid for any G.
+    // mapping is a permutation of the grid for any G.  Every other step (input copy 1) walks each run
+    // backwards: a step then starts on the tiles the previous one wrote last, whose populations are
+    // still in the last-level cache.
     const int G = gridDim.x;
     const int b = blockIdx.x;
-    const int slot = xcd_remap ? (b % 8) * (G / 8) + min(b % 8, G % 8) + b / 8 : b;
+    int slot = b;
+    if (xcd_remap) {
+        const int x = b % 8, k = b / 8, cnt = G / 8 + (x < G % 8 ? 1 : 0);
+        slot = x * (G / 8) + min(x, G % 8) + (par ? cnt - 1 - k : k);
+    }
 
     // halo position r of the ring: the RAD rows above and below the tile, then RAD columns left and
     // right of it
