@@ -69,12 +69,6 @@ __device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
     asm("" : "+s"(base));
     *(GMEM T*)(base + boff) = v;
 }
-// a load that streams past the caches, for populations that only their own cell reads
-template <class T>
-__device__ __forceinline__ T gld_stream(const GMEM char* base, uint32_t boff) {
-    asm("" : "+s"(base));
-    return __builtin_nontemporal_load((const GMEM T*)(base + boff));
-}
 
 template <bool FLOW, bool INOUT>
 __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ dp, int par, int xcd_remap) {
@@ -111,17 +105,16 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
     const uint32_t co = xp + yp + zp;
     const uint32_t cf = xpart(x, 1) + ypart(y, d.nbx, 1) + zpart(z, d.nbx, d.nby, 1);
 
-    // the cell's own flow, vapour and phi_prev first (streamed: no other block reads them, and the
-    // last-level cache is left to the populations the previous step wrote), then the halo box of h
+    // the cell's own flow, vapour and phi_prev first, then the halo box of h
     float f[19], g[7], phip = 0.f;
     if (active) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q) g[q] = gld_stream<float>(pin + (PG + q) * PB, co * 4);
+        for (int q = 0; q < 7; ++q) g[q] = gld<float>(pin + (PG + q) * PB, co * 4);
         if (FLOW) {
 #pragma unroll
-            for (int q = 0; q < 19; ++q) f[q] = gld_stream<float>(pin + (PF + q) * PB, co * 4);
+            for (int q = 0; q < 19; ++q) f[q] = gld<float>(pin + (PF + q) * PB, co * 4);
         }
-        phip = gld_stream<float>(phin, cf * 4);
+        phip = gld<float>(phin, cf * 4);
     }
     for (int p = tid; p < LN; p += kBlockCells) {
         const int lx = p % LX, ly = (p / LX) % LY, lz = p / (LX * LY);

@@ -49,13 +49,6 @@ __device__ __forceinline__ void gst(GMEM char* base, uint32_t boff, T v) {
     asm("" : "+s"(base));
     *(GMEM T*)(base + boff) = v;
 }
-// A load that streams past the caches (global_load ... nt): for populations read once per step, so
-// that they do not push the just-written populations of the other copy out of the last-level cache.
-template <class T>
-__device__ __forceinline__ T gld_stream(const GMEM char* base, uint32_t boff) {
-    asm("" : "+s"(base));
-    return __builtin_nontemporal_load((const GMEM T*)(base + boff));
-}
 
 struct DomDesc {
     int32_t nx, ny, nbx, npop;    // nbx: 64 x 4 blocks per block row; npop: planes per copy (23 with

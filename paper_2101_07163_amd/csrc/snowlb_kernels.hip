@@ -70,10 +70,6 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(kM
 k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int ntiles, int par, int xcd_remap) {
     using T = typename S::T;
     constexpr bool REF = S::kLocalRef;
-    // FP32 storage (805 MB of populations for 2048^2 against a 256 MB last-level cache) streams the
-    // cell's own f, g and phi_prev, which no other workgroup reads: 3 % faster with the alternating
-    // tile order; 16-bit storage keeps cached loads (7 % slower streamed)
-    constexpr bool STREAM = !REF;
     constexpr int NR = REF ? (FLOW ? 4 : 1) : 1;  // reference planes staged in LDS
     constexpr int NT = TX * TY;
     constexpr int LX = TX + 2 * RAD, LY = TY + 2 * RAD, LN = LX * LY;
@@ -171,7 +167,7 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         if (oreal) {
 #pragma unroll
             for (int q = 0; q < 9; ++q) hraw[q] = gld<T>(pin + (PH + q) * pb, oo.p * ES);
-            ophi = STREAM ? gld_stream<float>(phin, oo.f * 4) : gld<float>(phin, oo.f * 4);
+            ophi = gld<float>(phin, oo.f * 4);
             if (REF) {
 #pragma unroll
                 for (int k = 0; k < NR; ++k) oref[k] = gld<T>(rin + k * rb, oo.r * ES);
@@ -179,10 +175,10 @@ k_step(const DomDesc* __restrict__ doms, const TileDesc* __restrict__ tiles, int
         }
         if (active) {
 #pragma unroll
-            for (int q = 0; q < 5; ++q) graw[q] = STREAM ? gld_stream<T>(pin + (PG + q) * pb, co * ES) : gld<T>(pin + (PG + q) * pb, co * ES);
+            for (int q = 0; q < 5; ++q) graw[q] = gld<T>(pin + (PG + q) * pb, co * ES);
             if (FLOW) {
 #pragma unroll
-                for (int q = 0; q < 9; ++q) fraw[q] = STREAM ? gld_stream<T>(pin + (PF + q) * pb, co * ES) : gld<T>(pin + (PF + q) * pb, co * ES);
+                for (int q = 0; q < 9; ++q) fraw[q] = gld<T>(pin + (PF + q) * pb, co * ES);
             }
         }
         int rlx = 0, rly = 0;
