@@ -49,6 +49,12 @@ def impl_bytes_per_update(flow: bool, storage: str) -> int:
     return bytes_per_update(flow, storage) + refs
 
 
+def launch_name(grid_mode: int) -> str:
+    """The launch a grid mode selects: bit 0 persistent grid, bit 1 strip tile order."""
+    return "%s, %s" % ("persistent grid" if grid_mode & 1 else "one workgroup per tile",
+                       "512-cell strips" if grid_mode & 2 else "row order")
+
+
 def kernel_source_sha() -> str:
     """Hash of the step kernel's code (its source and the two headers it is built from), comments and
     blank space removed, so that only a change of that code marks counters as stale."""
@@ -378,8 +384,8 @@ def main():
     mlups = cells * args.steps / wall / 1e6
     bpu = bytes_per_update(flow, args.storage)
     achieved = cells * bpu / (kernel_ms * 1e-3) / 1e9
-    log("MLUPS %.1f (median of %d), step kernel %.4f ms, %.0f GB/s algorithmic, tile %s; repeats %s" % (
-        mlups, REPEATS, kernel_ms, achieved, S.snowlb_tile_name(sim.tile), reps))
+    log("MLUPS %.1f (median of %d), step kernel %.4f ms, %.0f GB/s algorithmic, tile %s, %s; repeats %s" % (
+        mlups, REPEATS, kernel_ms, achieved, S.snowlb_tile_name(sim.tile), launch_name(sim.grid_mode), reps))
     if diag["status"] != S.OK:
         raise SystemExit("non-finite state after the timed steps")
 
@@ -399,7 +405,8 @@ def main():
         "data": "synthetic: circular ice seed in uniform supersaturation with uniform inflow",
         "config": {"workload": cfg["name"], "nx": cfg["nx"], "ny": cfg["ny"], "storage": args.storage,
                    "flow": "D2Q9 inlet/outlet" if cfg.get("inout") else ("D2Q9 periodic" if flow else "off"),
-                   "u_in": cfg.get("u_in"), "eps": cfg["eps"], "tile": S.snowlb_tile_name(sim.tile)},
+                   "u_in": cfg.get("u_in"), "eps": cfg["eps"], "tile": S.snowlb_tile_name(sim.tile),
+                   "launch": launch_name(sim.grid_mode)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
@@ -424,6 +431,7 @@ def main():
             if st == args.storage or st not in wanted:
                 continue
             s2, w2, k2, _, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
+            launch2 = "%s, %s" % (S.snowlb_tile_name(s2.tile), launch_name(s2.grid_mode))
             b2 = bytes_per_update(flow, st)
             i2 = impl_bytes_per_update(flow, st)
             extras["%s_storage" % st] = {"MLUPS": round(cells * min(args.steps, 1000) / w2 / 1e6, 1),
@@ -432,7 +440,8 @@ def main():
                                          "frac_algorithmic": round(cells * b2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                          "bytes_per_update": b2,
                                          "impl_bytes_per_update": i2,
-                                         "GBps_impl": round(cells * i2 / (k2 * 1e-3) / 1e9, 1)}
+                                         "GBps_impl": round(cells * i2 / (k2 * 1e-3) / 1e9, 1),
+                                         "launch": launch2}
             log("%s storage: %s" % (st, extras["%s_storage" % st]))
             del s2
         if "stencils" in wanted:

@@ -56,12 +56,16 @@ snowlb_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SNOWL
 // ---------------------------------------------------------------------------------------------
 // Step driver: a device table of domain descriptors, one flat tile list per tile configuration,
 // the tile configuration and grid mode in use, the ping-pong parity and a captured graph.
+constexpr int kLaunchModes = 4;  // grid modes: bit 0 persistent grid, bit 1 strip tile order
+
 struct Driver {
     const DomDesc* d_doms = nullptr;  // owned by the caller
     std::vector<const DomDesc*> h_doms;  // host copies (geometry for the tile lists)
     int storage = 0, flow = 0, inout = 0, rad = 1;
+    // grid_mode (launch mode): bit 0 = persistent grid (else one workgroup per tile), bit 1 = strip
+    // tile order (else row order); see ensure_tiles
     int tile = 0, grid_mode = 0;
-    std::vector<TileDesc*> d_tiles;
+    std::vector<TileDesc*> d_tiles;  // per (tile configuration, order): index list_index(cfg, mode)
     std::vector<int> ntiles;
     int par = 0;
     int64_t step = 0;
@@ -93,8 +97,8 @@ struct Driver {
     snowlb_status hipfail(hipError_t e, const char* what) { return fail(hip_status(e), hip_msg(e, what)); }
 
     snowlb_status setup() {
-        d_tiles.assign(tile_config_count(), nullptr);
-        ntiles.assign(tile_config_count(), 0);
+        d_tiles.assign(2 * tile_config_count(), nullptr);
+        ntiles.assign(2 * tile_config_count(), 0);
         hipError_t e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hipfail(e, "hipStreamCreate");
         return SNOWLB_OK;
@@ -107,23 +111,27 @@ struct Driver {
         }
     }
 
-    snowlb_status ensure_tiles(int cfg) {
-        if (d_tiles[cfg]) return SNOWLB_OK;
+    static int list_index(int cfg, int mode) { return 2 * cfg + ((mode >> 1) & 1); }
+
+    // Tile list of configuration cfg in the order of launch mode `mode`.  Row order walks each lattice
+    // row of tiles by row of tiles.  Strip order cuts each lattice into vertical strips kStripCells
+    // wide and walks each strip row by row: a tile then shares its halo rows with tiles a strip's
+    // width away in the order instead of a lattice row away, but the halo columns at a strip's edges
+    // lie in tiles that run a whole strip later, often on another XCD.  Which wins depends on the
+    // lattice (2048^2: FP16 storage 0.1058 -> 0.0985 ms with strips, FP32 about even; 3000^2 and
+    // 6976 x 6692: strips 12-20 % slower; the 64-crystal batch 12 % slower), so the autotuner times
+    // both.  The order does not change any result.
+    snowlb_status ensure_tiles(int cfg, int mode) {
+        const int li = list_index(cfg, mode);
+        if (d_tiles[li]) return SNOWLB_OK;
         const int TX = tile_config_tx(cfg), TY = tile_config_ty(cfg);
         std::vector<TileDesc> t;
-        // Tile order: a lattice wider than 2 kStripCells is cut into vertical strips kStripCells wide,
-        // each strip walked row by row; narrower lattices are walked row by row.  In a strip a tile
-        // shares its halo rows with tiles a strip's width earlier and later in the order, which run on
-        // the same XCD close in time, instead of a full lattice row apart (2048^2 step: FP16 storage
-        // 0.1056 -> 0.0985 ms, FP32 0.1499 -> 0.1477 ms in one A/B; 256-cell strips slower again,
-        // 128-cell strips far slower).  On lattices up to 1024 cells wide strips lost (64-crystal batch:
-        // 29.1k -> 25.6k MLUPS): a row is already short, and the pushes across a strip's edge land in
-        // cache lines whose owner tile runs a whole strip later.  The order does not change any result.
         constexpr int kStripCells = 512;
+        const bool strips = (mode >> 1) & 1;
         for (size_t k = 0; k < h_doms.size(); ++k) {
             const DomDesc& dd = *h_doms[k];
             const int ntx = (dd.nx + TX - 1) / TX, nty = (dd.ny + TY - 1) / TY;
-            const int W = dd.nx > 2 * kStripCells ? std::max(1, kStripCells / TX) : ntx;
+            const int W = strips ? std::max(1, kStripCells / TX) : ntx;
             for (int s0 = 0; s0 < ntx; s0 += W)
                 for (int j = 0; j < nty; ++j)
                     for (int i = s0; i < std::min(ntx, s0 + W); ++i)
@@ -138,17 +146,18 @@ struct Driver {
             (void)hipFree(d);
             return hipfail(e, "hipMemcpy(tiles)");
         }
-        d_tiles[cfg] = d;
-        ntiles[cfg] = (int)t.size();
+        d_tiles[li] = d;
+        ntiles[li] = (int)t.size();
         return SNOWLB_OK;
     }
 
     snowlb_status plain(int cfg, int mode, int n, hipStream_t s) {
-        snowlb_status st = ensure_tiles(cfg);
+        snowlb_status st = ensure_tiles(cfg, mode);
         if (st) return st;
-        const int grid = step_grid(cfg, ntiles[cfg], storage, flow, inout, rad, mode);
+        const int li = list_index(cfg, mode);
+        const int grid = step_grid(cfg, ntiles[li], storage, flow, inout, rad, mode & 1);
         for (int i = 0; i < n; ++i) {
-            hipError_t e = launch_step(cfg, storage, flow, inout, rad, d_doms, d_tiles[cfg], ntiles[cfg], grid, par, s);
+            hipError_t e = launch_step(cfg, storage, flow, inout, rad, d_doms, d_tiles[li], ntiles[li], grid, par, s);
             if (e != hipSuccess) return hipfail(e, "step kernel launch");
             par ^= 1;
             step += 1;
@@ -163,12 +172,13 @@ struct Driver {
         if (G.exec && G.steps == K && G.tile == tile && G.mode == grid_mode) return SNOWLB_OK;
         if (G.exec) (void)hipGraphExecDestroy(G.exec);
         G = StepGraph{};
-        const int grid = step_grid(tile, ntiles[tile], storage, flow, inout, rad, grid_mode);
+        const int li = list_index(tile, grid_mode);
+        const int grid = step_grid(tile, ntiles[li], storage, flow, inout, rad, grid_mode & 1);
         hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hipfail(e, "hipStreamBeginCapture");
         hipError_t le = hipSuccess;
         for (int i = 0; i < K && le == hipSuccess; ++i)
-            le = launch_step(tile, storage, flow, inout, rad, d_doms, d_tiles[tile], ntiles[tile], grid, i & 1,
+            le = launch_step(tile, storage, flow, inout, rad, d_doms, d_tiles[li], ntiles[li], grid, i & 1,
                              cap_stream);
         hipGraph_t g = nullptr;
         hipError_t ee = hipStreamEndCapture(cap_stream, &g);
@@ -199,7 +209,7 @@ struct Driver {
     // if the state sits in copy 1 (the graphs start from copy 0), then whole graphs of K steps while
     // at least K remain, then graphs of two steps, and a single launch for an odd last step.
     snowlb_status run(int n, hipStream_t s) {
-        snowlb_status st = ensure_tiles(tile);
+        snowlb_status st = ensure_tiles(tile, grid_mode);
         if (st) return st;
         const int K = std::max(2, env_int("SNOWLB_GRAPH_STEPS", 32) & ~1);
         if (env_int("SNOWLB_NO_GRAPH", 0)) return plain(tile, grid_mode, n, s);
@@ -221,9 +231,9 @@ struct Driver {
         return plain(tile, grid_mode, n, s);
     }
 
-    // Time every (tile configuration, grid mode) on the current state and keep the fastest: all
-    // candidates first run 2 warm-up steps each (code objects loaded, tile lists built), then each
-    // runs `reps` timed steps three times and its median is kept.  save / restore bracket the
+    // Time every (tile configuration, grid mode: launch shape and tile order) on the current state and
+    // keep the fastest: all candidates first run 2 warm-up steps each (code objects loaded, tile lists
+    // built), then each runs `reps` timed steps three times and its median is kept.  save / restore bracket the
     // trials, so tuning does not change the simulation.
     snowlb_status autotune(hipStream_t s, const std::function<snowlb_status()>& save,
                            const std::function<snowlb_status()>& restore) {
@@ -241,9 +251,9 @@ struct Driver {
         const int par0 = par;
         const int64_t step0 = step;
         for (int cfg = 0; cfg < tile_config_count() && !st; ++cfg)
-            for (int mode = 0; mode < 2 && !st; ++mode) st = plain(cfg, mode, 2, s);
+            for (int mode = 0; mode < kLaunchModes && !st; ++mode) st = plain(cfg, mode, 2, s);
         for (int cfg = 0; cfg < tile_config_count() && !st; ++cfg)
-            for (int mode = 0; mode < 2 && !st; ++mode) {
+            for (int mode = 0; mode < kLaunchModes && !st; ++mode) {
                 float t[3];
                 for (int r = 0; r < 3 && !st; ++r) {
                     (void)hipEventRecord(e0, s);
@@ -256,7 +266,9 @@ struct Driver {
                 }
                 if (st) break;
                 std::sort(t, t + 3);
-                if (t[1] < best_ms) {
+                // a later candidate must be 1 % faster to replace the incumbent, so that near-ties
+                // keep the first (simplest) configuration from run to run
+                if (t[1] < 0.99f * best_ms) {
                     best_ms = t[1];
                     best = cfg;
                     best_mode = mode;
@@ -287,7 +299,7 @@ std::string tune_cache_path() {
 // lattice and "<layout> batch <ndomains> <cells> storage flow bc" for a batch; <layout> names the
 // memory layout the timings were taken on, so a library with another layout re-tunes.  The last
 // matching line wins.
-constexpr const char* kTuneLayout = "L5";
+constexpr const char* kTuneLayout = "L6";
 // The cache may be shared by several processes: readers take a shared lock, writers an exclusive one.
 bool tune_lookup(const std::string& key, int& tile, int& mode) {
     FILE* f = std::fopen(tune_cache_path().c_str(), "r");
@@ -904,7 +916,7 @@ int32_t snowlb_get_tile(const snowlb_ctx* c) { return c ? c->drv.tile : -1; }
 
 snowlb_status snowlb_set_grid_mode(snowlb_ctx* c, int32_t mode) {
     if (!c) return SNOWLB_EINVAL;
-    if (mode != 0 && mode != 1) return fail(c, SNOWLB_EINVAL, "grid mode must be 0 or 1");
+    if (mode < 0 || mode >= kLaunchModes) return fail(c, SNOWLB_EINVAL, "grid mode must be 0, 1, 2 or 3");
     c->drv.grid_mode = mode;
     c->tuned = true;
     c->drv.drop_graph();
@@ -1003,7 +1015,7 @@ static snowlb_status adj_graph(snowlb_ctx* c, int kind, AdjDesc A, float* const 
         key.cur = cur;
     } else {
         key.segdoms = c->adj.d_segdoms;
-        key.tiles = D.d_tiles[D.tile];
+        key.tiles = D.d_tiles[Driver::list_index(D.tile, D.grid_mode)];
         key.tile = D.tile;
         key.grid = grid;
         key.storage = c->p.storage;
@@ -1027,7 +1039,8 @@ static snowlb_status adj_graph(snowlb_ctx* c, int kind, AdjDesc A, float* const 
     if (kind == 0) {
         const DomDesc* sd = c->adj.d_segdoms + (int64_t)area * std::max(c->adj.stride - 1, 1);
         for (int i = 0; i + 1 < len && le == hipSuccess; ++i)
-            le = launch_step(D.tile, c->p.storage, 0, 0, 1, sd + i, D.d_tiles[D.tile], D.ntiles[D.tile], grid, 0, cs);
+            le = launch_step(D.tile, c->p.storage, 0, 0, 1, sd + i, D.d_tiles[Driver::list_index(D.tile, D.grid_mode)],
+                             D.ntiles[Driver::list_index(D.tile, D.grid_mode)], grid, 0, cs);
     } else {
         const int64_t base = adj_area_slot(c, area);
         for (int i = len - 1; i >= 0 && le == hipSuccess; --i) {
@@ -1128,9 +1141,10 @@ snowlb_status snowlb_adj_backward(snowlb_ctx* c, const float* dphi, float* dU, d
     hipError_t e = launch_adj_seed(A, dphi, s);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint seed kernel");
     Driver& D = c->drv;
-    snowlb_status r = from_driver(c, D.ensure_tiles(D.tile));
+    snowlb_status r = from_driver(c, D.ensure_tiles(D.tile, D.grid_mode));
     if (r) return r;
-    const int grid = step_grid(D.tile, D.ntiles[D.tile], c->p.storage, 0, 0, 1, D.grid_mode);
+    const int grid = step_grid(D.tile, D.ntiles[Driver::list_index(D.tile, D.grid_mode)], c->p.storage, 0, 0, 1,
+                               D.grid_mode & 1);
     // Checkpoint intervals are reversed from the last to the first.  Interval k lives in segment area
     // k % 2: its checkpoint is copied into the area's first slot, (len - 1) recompute steps fill the
     // rest, and len reverse steps consume it.  With overlap (the default), interval k - 1 is
@@ -1362,7 +1376,7 @@ snowlb_status snowlb_batch_diag(snowlb_batch* b, int32_t i, double* out, void* s
 
 snowlb_status snowlb_batch_set_tile(snowlb_batch* b, int32_t tile, int32_t mode) {
     if (!b) return SNOWLB_EINVAL;
-    if (tile < 0 || tile >= tile_config_count() || (mode != 0 && mode != 1)) {
+    if (tile < 0 || tile >= tile_config_count() || mode < 0 || mode >= kLaunchModes) {
         b->err = "unknown tile configuration or grid mode";
         return SNOWLB_EINVAL;
     }
