@@ -89,13 +89,15 @@ def load_traffic(workload: str, storage: str):
 REPEATS = 5  # timed repeats of the K steps; the median is reported
 
 
-def time_steps(S, torch, cfg, storage, steps, warmup, tile, repeats=REPEATS):
+def time_steps(S, torch, cfg, storage, steps, warmup, tile, repeats=REPEATS, grid_mode=-1):
     """W untimed warm-up steps, then `repeats` timed runs of exactly `steps` steps, each bracketed by
     device synchronisation, replayed from captured graphs on the current stream; the kernel time per
     step comes from events on that stream.  Returns the median wall time, the median event time per
     step, the timings of every repeat, and the FP64 diagnostics taken after the timed runs (their
     synchronisation is timed on its own)."""
     sim = S.Sim(cfg, storage=storage, tile=tile)
+    if grid_mode >= 0:
+        sim.set_grid_mode(grid_mode)
     sim.init()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -350,6 +352,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--tile", type=int, default=-1, help="-1: autotune")
+    ap.add_argument("--grid-mode", type=int, default=-1,
+                    help="with --tile >= 0: launch mode (bit 0 persistent grid, bit 1 strip tile order)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -358,6 +362,8 @@ def main():
                          "c4 (64-crystal batch), c5 (adjoint/forward time ratio), stencils, table2 (habit "
                          "sweep), f4 (the 3D extension)")
     args = ap.parse_args()
+    if args.grid_mode >= 0 and args.tile < 0:
+        ap.error("--grid-mode needs an explicit --tile (with --tile -1 the autotuner picks both)")
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -380,7 +386,8 @@ def main():
 
     log("workload %s %dx%d storage %s: warmup %d, timed %d steps" % (
         cfg["name"], cfg["nx"], cfg["ny"], args.storage, args.warmup, args.steps))
-    sim, wall, kernel_ms, diag, reps = time_steps(S, torch, cfg, args.storage, args.steps, args.warmup, args.tile)
+    sim, wall, kernel_ms, diag, reps = time_steps(S, torch, cfg, args.storage, args.steps, args.warmup, args.tile,
+                                                   grid_mode=args.grid_mode)
     mlups = cells * args.steps / wall / 1e6
     bpu = bytes_per_update(flow, args.storage)
     achieved = cells * bpu / (kernel_ms * 1e-3) / 1e9
@@ -430,7 +437,8 @@ def main():
         for st in ("fp16", "bf16"):
             if st == args.storage or st not in wanted:
                 continue
-            s2, w2, k2, _, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile)
+            s2, w2, k2, _, _ = time_steps(S, torch, cfg, st, min(args.steps, 1000), 100, args.tile,
+                                          grid_mode=args.grid_mode)
             launch2 = "%s, %s" % (S.snowlb_tile_name(s2.tile), launch_name(s2.grid_mode))
             b2 = bytes_per_update(flow, st)
             i2 = impl_bytes_per_update(flow, st)
