@@ -50,9 +50,9 @@ def impl_bytes_per_update(flow: bool, storage: str) -> int:
 
 
 def launch_name(grid_mode: int) -> str:
-    """The launch a grid mode selects: bit 0 persistent grid, bit 1 strip tile order."""
+    """The launch a grid mode selects: bit 0 persistent grid, grid_mode >> 1 the tile order."""
     return "%s, %s" % ("persistent grid" if grid_mode & 1 else "one workgroup per tile",
-                       "512-cell strips" if grid_mode & 2 else "row order")
+                       ("row order", "512-cell strips", "four strips")[grid_mode >> 1])
 
 
 def kernel_source_sha() -> str:
@@ -67,10 +67,14 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload: str, storage: str):
-    """Measured HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; None otherwise."""
-    p = os.path.join(ROOT, "profiles", "k_step_%s_%s_traffic.txt" % (workload, storage))
+ORDER_SUFFIX = {0: "", 1: "_strips", 2: "_four_strips"}  # tile order (grid_mode >> 1) -> summary name
+
+
+def load_traffic(workload: str, storage: str, tile: str = "64x4", grid_mode: int = 0):
+    """Measured HBM bytes per launch from the committed rocprofv3 counter summary of this launch (tile
+    shape and grid mode), if it was taken on the current kernel source; None otherwise."""
+    p = os.path.join(ROOT, "profiles", "k_step_%s_%s%s_traffic.txt" % (
+        workload, storage, ORDER_SUFFIX.get(grid_mode >> 1, "_unknown")))
     if not os.path.exists(p):
         return None
     kv = {}
@@ -79,6 +83,8 @@ def load_traffic(workload: str, storage: str):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    if kv.get("tile", tile) != tile or kv.get("grid_mode", str(grid_mode)) != str(grid_mode):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -353,7 +359,8 @@ def main():
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--tile", type=int, default=-1, help="-1: autotune")
     ap.add_argument("--grid-mode", type=int, default=-1,
-                    help="with --tile >= 0: launch mode (bit 0 persistent grid, bit 1 strip tile order)")
+                    help="with --tile >= 0: launch mode (bit 0 persistent grid; mode >> 1: 0 row order, "
+                         "1 512-cell strips, 2 four strips)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -396,7 +403,7 @@ def main():
     if diag["status"] != S.OK:
         raise SystemExit("non-finite state after the timed steps")
 
-    traffic = load_traffic(cfg["name"], args.storage)
+    traffic = load_traffic(cfg["name"], args.storage, S.snowlb_tile_name(sim.tile), sim.grid_mode)
     out = {
         "metric": "coupled MLUPS and % HBM roofline at 2048^2; adjoint/forward time ratio",
         "value": round(mlups, 2),

@@ -209,11 +209,11 @@ snowlb_status snowlb_load_state(snowlb_ctx* ctx, const void* buf_dev, int64_t by
 
 /* Step-kernel tile configurations.  snowlb_tile_count() configurations exist; snowlb_tile_name(i)
  * describes one ("64x4" = 64 cells in x by 4 in y per workgroup).  snowlb_set_tile selects one for
- * a context; results are bitwise identical for every configuration.  Grid modes (0..3): bit 0 selects
- * a persistent grid of resident workgroups looping over the tiles (else one workgroup per tile), bit 1
- * the strip tile order (the lattice cut into vertical strips 512 cells wide, each walked row by row;
- * else row order).  0 is the default; the autotuner (tile = -1) times all four.  Other values are
- * rejected with SNOWLB_EINVAL. */
+ * a context; results are bitwise identical for every configuration.  Grid modes (0..5): bit 0 selects
+ * a persistent grid of resident workgroups looping over the tiles (else one workgroup per tile);
+ * grid_mode >> 1 the tile order: 0 row order, 1 vertical strips 512 cells wide, 2 four vertical strips
+ * of nearly equal width (each strip walked row by row).  0 is the default; the autotuner (tile = -1)
+ * times all six.  Other values are rejected with SNOWLB_EINVAL. */
 int32_t snowlb_tile_count(void);
 const char* snowlb_tile_name(int32_t i);
 snowlb_status snowlb_set_tile(snowlb_ctx* ctx, int32_t tile);

@@ -56,14 +56,15 @@ snowlb_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? SNOWL
 // ---------------------------------------------------------------------------------------------
 // Step driver: a device table of domain descriptors, one flat tile list per tile configuration,
 // the tile configuration and grid mode in use, the ping-pong parity and a captured graph.
-constexpr int kLaunchModes = 4;  // grid modes: bit 0 persistent grid, bit 1 strip tile order
+// grid modes: bit 0 persistent grid; mode >> 1 the tile order (0 rows, 1 512-cell strips, 2 four strips)
+constexpr int kTileOrders = 3, kLaunchModes = 2 * kTileOrders;
 
 struct Driver {
     const DomDesc* d_doms = nullptr;  // owned by the caller
     std::vector<const DomDesc*> h_doms;  // host copies (geometry for the tile lists)
     int storage = 0, flow = 0, inout = 0, rad = 1;
-    // grid_mode (launch mode): bit 0 = persistent grid (else one workgroup per tile), bit 1 = strip
-    // tile order (else row order); see ensure_tiles
+    // grid_mode (launch mode): bit 0 = persistent grid (else one workgroup per tile), grid_mode >> 1 =
+    // tile order; see ensure_tiles
     int tile = 0, grid_mode = 0;
     std::vector<TileDesc*> d_tiles;  // per (tile configuration, order): index list_index(cfg, mode)
     std::vector<int> ntiles;
@@ -97,8 +98,8 @@ struct Driver {
     snowlb_status hipfail(hipError_t e, const char* what) { return fail(hip_status(e), hip_msg(e, what)); }
 
     snowlb_status setup() {
-        d_tiles.assign(2 * tile_config_count(), nullptr);
-        ntiles.assign(2 * tile_config_count(), 0);
+        d_tiles.assign(kTileOrders * tile_config_count(), nullptr);
+        ntiles.assign(kTileOrders * tile_config_count(), 0);
         hipError_t e = hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hipfail(e, "hipStreamCreate");
         return SNOWLB_OK;
@@ -111,27 +112,30 @@ struct Driver {
         }
     }
 
-    static int list_index(int cfg, int mode) { return 2 * cfg + ((mode >> 1) & 1); }
+    static int list_index(int cfg, int mode) { return kTileOrders * cfg + (mode >> 1); }
 
     // Tile list of configuration cfg in the order of launch mode `mode`.  Row order walks each lattice
-    // row of tiles by row of tiles.  Strip order cuts each lattice into vertical strips kStripCells
-    // wide and walks each strip row by row: a tile then shares its halo rows with tiles a strip's
-    // width away in the order instead of a lattice row away, but the halo columns at a strip's edges
-    // lie in tiles that run a whole strip later, often on another XCD.  Which wins depends on the
-    // lattice (2048^2: FP16 storage 0.1058 -> 0.0985 ms with strips, FP32 about even; 3000^2 and
-    // 6976 x 6692: strips 12-20 % slower; the 64-crystal batch 12 % slower), so the autotuner times
-    // both.  The order does not change any result.
+    // row of tiles by row of tiles.  The strip orders cut each lattice into vertical strips, 512 cells
+    // wide (order 1) or four of nearly equal width (order 2), and walk each strip row by row: a tile
+    // then shares its halo rows with tiles a strip's width away in the order instead of a lattice row
+    // away, but the halo columns at a strip's edges lie in tiles that may run much later, on another
+    // XCD.  Strips pay where each strip is a whole number of the XCDs' runs of the list, so that the
+    // XCDs on the two sides of an edge walk it at the same time; which order wins depends on the
+    // lattice (2048^2 FP16 storage: 0.1058 -> 0.0988 ms with either strip order, FP32 about even;
+    // 1536^2 and 4096 x 2048: four strips 2-5 % faster; 3000^2, 6976 x 6692, 1024^2 and the
+    // 64-crystal batch: strips 3-20 % slower), so the autotuner times every order.  The order does
+    // not change any result.
     snowlb_status ensure_tiles(int cfg, int mode) {
         const int li = list_index(cfg, mode);
         if (d_tiles[li]) return SNOWLB_OK;
         const int TX = tile_config_tx(cfg), TY = tile_config_ty(cfg);
         std::vector<TileDesc> t;
         constexpr int kStripCells = 512;
-        const bool strips = (mode >> 1) & 1;
+        const int order = mode >> 1;
         for (size_t k = 0; k < h_doms.size(); ++k) {
             const DomDesc& dd = *h_doms[k];
             const int ntx = (dd.nx + TX - 1) / TX, nty = (dd.ny + TY - 1) / TY;
-            const int W = strips ? std::max(1, kStripCells / TX) : ntx;
+            const int W = order == 1 ? std::max(1, kStripCells / TX) : order == 2 ? (ntx + 3) / 4 : ntx;
             for (int s0 = 0; s0 < ntx; s0 += W)
                 for (int j = 0; j < nty; ++j)
                     for (int i = s0; i < std::min(ntx, s0 + W); ++i)
@@ -299,7 +303,7 @@ std::string tune_cache_path() {
 // lattice and "<layout> batch <ndomains> <cells> storage flow bc" for a batch; <layout> names the
 // memory layout the timings were taken on, so a library with another layout re-tunes.  The last
 // matching line wins.
-constexpr const char* kTuneLayout = "L6";
+constexpr const char* kTuneLayout = "L7";
 // The cache may be shared by several processes: readers take a shared lock, writers an exclusive one.
 bool tune_lookup(const std::string& key, int& tile, int& mode) {
     FILE* f = std::fopen(tune_cache_path().c_str(), "r");
@@ -916,7 +920,7 @@ int32_t snowlb_get_tile(const snowlb_ctx* c) { return c ? c->drv.tile : -1; }
 
 snowlb_status snowlb_set_grid_mode(snowlb_ctx* c, int32_t mode) {
     if (!c) return SNOWLB_EINVAL;
-    if (mode < 0 || mode >= kLaunchModes) return fail(c, SNOWLB_EINVAL, "grid mode must be 0, 1, 2 or 3");
+    if (mode < 0 || mode >= kLaunchModes) return fail(c, SNOWLB_EINVAL, "grid mode must be 0..5");
     c->drv.grid_mode = mode;
     c->tuned = true;
     c->drv.drop_graph();

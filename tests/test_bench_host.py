@@ -70,6 +70,15 @@ def test_traffic_only_from_a_summary_of_the_current_kernel(tree_copy):
     assert bench.load_traffic("wl", "fp32") == 1234.0
     p.write_text("kernel_source_sha: 0000000000000000\nhbm_bytes_per_launch: 1234.0\n")
     assert bench.load_traffic("wl", "fp32") is None  # taken on another kernel
+    # a summary names its launch; another tile shape or grid mode does not use it
+    p.write_text("kernel_source_sha: %s\ntile: 64x4\ngrid_mode: 0\nhbm_bytes_per_launch: 99.0\n" % bench.kernel_source_sha())
+    assert bench.load_traffic("wl", "fp32", "64x4", 0) == 99.0
+    assert bench.load_traffic("wl", "fp32", "64x4", 1) is None
+    assert bench.load_traffic("wl", "fp32", "128x2", 0) is None
+    assert bench.load_traffic("wl", "fp32", "64x4", 2) is None  # strip order: its own summary
+    (tree_copy / "profiles" / "k_step_wl_fp32_strips_traffic.txt").write_text(
+        "kernel_source_sha: %s\ntile: 64x4\ngrid_mode: 2\nhbm_bytes_per_launch: 98.0\n" % bench.kernel_source_sha())
+    assert bench.load_traffic("wl", "fp32", "64x4", 2) == 98.0
 
 
 def test_committed_traffic_summary_names_its_kernel_hash():

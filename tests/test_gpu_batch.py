@@ -32,7 +32,7 @@ def fields(get):
     return {k: get(k).cpu().numpy() for k in ("phi", "U", "rho", "ux", "uy")}
 
 
-@pytest.mark.parametrize("tile,grid_mode", [(0, 0), (3, 1), (5, 0), (0, 2), (2, 3)])
+@pytest.mark.parametrize("tile,grid_mode", [(0, 0), (3, 1), (5, 0), (0, 2), (2, 3), (1, 4)])
 def test_batched_equals_solo_bitwise(tile, grid_mode):
     cfgs = small_domains()
     b = S.Batch(cfgs).set_tile(tile, grid_mode).init()

@@ -155,15 +155,15 @@ def test_tile_configurations_bitwise_identical(case, storage, stencil):
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
 def test_tile_orders_and_grid_modes_bitwise_identical(storage):
-    """Every grid mode (one workgroup per tile or a persistent grid; row or 512-cell strip tile order)
-    gives the same bits, on a ventilated lattice wide enough for three strips (the last one ragged),
-    through plain launches and graph replays.  Modes outside 0..3 are rejected."""
+    """Every grid mode (one workgroup per tile or a persistent grid; row order, 512-cell strips or four
+    strips) gives the same bits, on a ventilated lattice wide enough for three 512-cell strips (the last
+    one ragged), through plain launches and graph replays.  Modes outside 0..5 are rejected."""
     nx, ny = 1100, 45
     cfg = cfg_of(nx, ny, **CASES["flow_inout"])
     st = {k: torch.from_numpy(f32(v)) for k, v in W.random_state(nx, ny, seed=9, flow=True).items()}
     ref = None
     for t in (0, 2):
-        for mode in range(4):
+        for mode in range(6):
             sim = S.Sim(cfg, tile=t, storage=storage)
             sim.set_grid_mode(mode)
             assert sim.grid_mode == mode
@@ -175,7 +175,7 @@ def test_tile_orders_and_grid_modes_bitwise_identical(storage):
             else:
                 for k in ref:
                     assert np.array_equal(ref[k], got[k]), (S.snowlb_tile_name(t), mode, k)
-    for bad in (-1, 4):
+    for bad in (-1, 6):
         with pytest.raises(S.SnowlbError):
             sim.set_grid_mode(bad)
 
