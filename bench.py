@@ -70,6 +70,17 @@ def kernel_source_sha() -> str:
 ORDER_SUFFIX = {0: "", 1: "_strips", 2: "_four_strips"}  # tile order (grid_mode >> 1) -> summary name
 
 
+def kernel3_source_sha() -> str:
+    """The same hash for the 3D step kernel (its source and its descriptor header)."""
+    h = hashlib.sha256()
+    for name in ("snowlb3d_kernels.hip", "snowlb3d_internal.h"):
+        for line in open(os.path.join(ROOT, "paper_2101_07163_amd", "csrc", name)):
+            code = line.split("//", 1)[0].strip()
+            if code:
+                h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
 def load_traffic(workload: str, storage: str, tile: str = "64x4", grid_mode: int = 0):
     """Measured HBM bytes per launch from the committed rocprofv3 counter summary of this launch (tile
     shape and grid mode), if it was taken on the current kernel source; None otherwise."""

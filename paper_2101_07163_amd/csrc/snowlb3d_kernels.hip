@@ -82,14 +82,17 @@ __global__ void __launch_bounds__(kBlockCells) k_step3(const Dom3* __restrict__ 
 
     const int tid = threadIdx.x;
     const int tx = tid & (kBX - 1), ty = (tid >> kSX) & (kBY - 1), tz = tid >> (kSX + kSY);
-    // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid),
-    // walked backwards every other step (input copy 1), so that a step starts on the blocks the
-    // previous one wrote last, which are still in the last-level cache
+    // XCD-aware order: each of the 8 XCDs takes a contiguous run of blocks (a permutation for any grid).
+    // Odd and even XCDs walk their runs in opposite directions, so the two XCDs on either side of a
+    // shared z-slab boundary reach it at the same time and its halo lines meet in the last-level cache;
+    // every XCD turns round every other step (input copy 1), so that a step starts on the blocks the
+    // previous one wrote last, which are still in that cache (0.2418 -> 0.2386 ms on the 256 x 128 x 128
+    // step against the same direction for all XCDs)
     const int G = gridDim.x, b = blockIdx.x;
     int t = b;
     if (xcd_remap) {
         const int x = b % 8, k = b / 8, cnt = G / 8 + (x < G % 8 ? 1 : 0);
-        t = x * (G / 8) + min(x, G % 8) + (par ? cnt - 1 - k : k);
+        t = x * (G / 8) + min(x, G % 8) + (((x & 1) ^ par) ? cnt - 1 - k : k);
     }
     const int bx = t % d.nbx, by = (t / d.nbx) % d.nby, bz = t / (d.nbx * d.nby);
     const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
