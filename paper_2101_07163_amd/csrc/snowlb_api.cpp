@@ -321,7 +321,7 @@ bool tune_lookup(const std::string& key, int& tile, int& mode) {
         if (l.substr(0, a) != key) continue;
         const int t = std::atoi(l.substr(a + 1, b - a - 1).c_str());
         const int m = std::atoi(l.substr(b + 1).c_str());
-        if (t >= 0 && t < tile_config_count() && (m == 0 || m == 1)) {
+        if (t >= 0 && t < tile_config_count() && m >= 0 && m < kLaunchModes) {
             tile = t;
             mode = m;
             found = true;

@@ -180,6 +180,25 @@ def test_tile_orders_and_grid_modes_bitwise_identical(storage):
             sim.set_grid_mode(bad)
 
 
+def test_tune_cache_round_trip_keeps_every_grid_mode(tmp_path, monkeypatch):
+    """The autotuner stores its pick in the tune cache, and a later context of the same lattice reads
+    it back, strip orders (grid modes 2..5) included; a line with an unknown mode is ignored."""
+    monkeypatch.setenv("SNOWLB_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    cfg = cfg_of(1100, 45, **CASES["flow_inout"])
+    a = S.Sim(cfg, tile=-1).init().step(4)  # tunes on the first step and stores the pick
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1
+    key, t, m = lines[0].rsplit(" ", 2)
+    assert (int(t), int(m)) == (a.tile, a.grid_mode)
+    for mode in range(6):
+        (tmp_path / "tune.txt").write_text("%s 1 %d\n" % (key, mode))
+        b = S.Sim(cfg, tile=-1).init().step(2)
+        assert (b.tile, b.grid_mode) == (1, mode)
+    (tmp_path / "tune.txt").write_text("%s 1 3\n%s 2 6\n" % (key, key))  # the second line is invalid
+    b = S.Sim(cfg, tile=-1).init().step(2)
+    assert (b.tile, b.grid_mode) == (1, 3)
+
+
 def test_init_matches_oracle():
     for case in CASES:
         cfg = cfg_of(96, 80, **CASES[case])
